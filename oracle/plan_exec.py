@@ -1,0 +1,78 @@
+"""Executor for an exported cache-blocked plan (TEST INFRASTRUCTURE ONLY).
+
+It gives a transpiled op list its meaning (Sec. IV-A, the transpilation for
+cache blocking, and Sec. IV-C, the chunk update loop) so that a plan can be
+checked against the plain circuit:
+
+  ('begin', local_mask)       begin_blocking: the next gates must act only on
+                              the physical bits in local_mask (the chunk)
+  ('end',)                    end_blocking
+  ('swap', a, b)              chunk_swap of physical bits a and b: a noiseless
+                              SWAP, i.e. amplitudes move
+  ('gate', index, phys)       gate ``gates[index]`` applied on physical qubits
+                              ``phys`` (same order as the gate's own tuple)
+
+After the last op, logical qubit q sits at physical bit final_perm[q]; the
+state is returned in logical order (Fig. "chunk_swap" case (b): reorder for
+output).
+"""
+
+import numpy as np
+
+from .gates import is_diagonal_kind
+from .statevector import apply_gate
+
+
+def _unpermute(psi, n, final_perm):
+    """out[x] = psi[y] with bit final_perm[q] of y equal to bit q of x."""
+    if list(final_perm) == list(range(n)):
+        return psi
+    x = np.arange(1 << n, dtype=np.int64)
+    y = np.zeros_like(x)
+    for q in range(n):
+        y |= ((x >> q) & 1) << int(final_perm[q])
+    return psi[y]
+
+
+def run_plan(n, gates, ops, final_perm, chunk_bits, diag_free=False, psi=None,
+             check_local=True):
+    """Execute ``ops`` on ``psi`` (default |0>), checking locality on the way.
+
+    Raises AssertionError if a gate inside a section touches a non-local bit
+    (diagonal gates are exempt when ``diag_free``), if a section's chunk does
+    not hold exactly ``chunk_bits`` bits (fewer when n < chunk_bits), or if a
+    gate is used a number of times other than once.
+    """
+    from .statevector import zero_state
+    psi = zero_state(n) if psi is None else np.array(psi, dtype=np.complex128, copy=True)
+    used = np.zeros(len(gates), dtype=np.int64)
+    local = None
+    for op in ops:
+        tag = op[0]
+        if tag == "begin":
+            assert local is None, "nested begin_blocking"
+            local = int(op[1])
+            assert bin(local).count("1") == min(chunk_bits, n), "chunk must hold %d bits" % min(chunk_bits, n)
+        elif tag == "end":
+            assert local is not None, "end_blocking without begin"
+            local = None
+        elif tag == "swap":
+            assert local is None, "chunk_swap inside a section"
+            a, b = int(op[1]), int(op[2])
+            apply_gate(psi, n, ("swap", (a, b), (), None, -1))
+        elif tag == "gate":
+            idx, phys = int(op[1]), tuple(int(q) for q in op[2])
+            kind, qubits, params, matrix, pidx = gates[idx]
+            assert len(phys) == len(qubits)
+            if check_local:
+                assert local is not None, "gate outside a section"
+                if not (diag_free and is_diagonal_kind(kind)):
+                    for q in phys:
+                        assert (local >> q) & 1, "gate %d touches non-local bit %d" % (idx, q)
+            used[idx] += 1
+            apply_gate(psi, n, (kind, phys, params, matrix, pidx))
+        else:
+            raise ValueError("unknown op %r" % (op,))
+    assert local is None, "unterminated section"
+    assert np.all(used == 1), "every gate must appear exactly once"
+    return _unpermute(psi, n, final_perm)
