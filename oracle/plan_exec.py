@@ -19,8 +19,27 @@ output).
 
 import numpy as np
 
-from .gates import is_diagonal_kind
+from .gates import gate_matrix
 from .statevector import apply_gate
+
+
+def diagonal_qubit_positions(kind, params, matrix):
+    """Positions j of the gate's qubit tuple in which its matrix is block
+    diagonal (U[a, b] = 0 whenever bit j of a and b differ): a phase depends on
+    that qubit (Sec. V-A: diagonal gates act on each amplitude on its own) or it
+    is a control.  Such a qubit need not be in the chunk: its value is fixed
+    per chunk when it is not local."""
+    u, k = gate_matrix(kind, params, matrix)
+    out = []
+    for j in range(k):
+        ok = True
+        for a in range(1 << k):
+            for b in range(1 << k):
+                if ((a >> j) & 1) != ((b >> j) & 1) and u[a, b] != 0:
+                    ok = False
+        if ok:
+            out.append(j)
+    return out
 
 
 def _unpermute(psi, n, final_perm):
@@ -39,7 +58,8 @@ def run_plan(n, gates, ops, final_perm, chunk_bits, diag_free=False, psi=None,
     """Execute ``ops`` on ``psi`` (default |0>), checking locality on the way.
 
     Raises AssertionError if a gate inside a section touches a non-local bit
-    (diagonal gates are exempt when ``diag_free``), if a section's chunk does
+    (with ``diag_free``, qubits in which the gate is block diagonal -- every
+    qubit of a phase gate, the control of a CX -- are exempt), if a section's chunk does
     not hold exactly ``chunk_bits`` bits (fewer when n < chunk_bits), or if a
     gate is used a number of times other than once.
     """
@@ -66,8 +86,9 @@ def run_plan(n, gates, ops, final_perm, chunk_bits, diag_free=False, psi=None,
             assert len(phys) == len(qubits)
             if check_local:
                 assert local is not None, "gate outside a section"
-                if not (diag_free and is_diagonal_kind(kind)):
-                    for q in phys:
+                exempt = diagonal_qubit_positions(kind, params, matrix) if diag_free else []
+                for j, q in enumerate(phys):
+                    if j not in exempt:
                         assert (local >> q) & 1, "gate %d touches non-local bit %d" % (idx, q)
             used[idx] += 1
             apply_gate(psi, n, (kind, phys, params, matrix, pidx))

@@ -103,3 +103,26 @@ def test_chunk_swap_case_b():
             assert np.array_equal(cout[ci], cin[ci ^ b0 ^ b1])
         else:
             assert np.array_equal(cout[ci], cin[ci])
+
+
+def test_diagonal_qubit_positions():
+    from oracle.plan_exec import diagonal_qubit_positions
+    assert diagonal_qubit_positions("cx", (), None) == [0]          # control only
+    assert diagonal_qubit_positions("cp", (0.3,), None) == [0, 1]
+    assert diagonal_qubit_positions("h", (), None) == []
+    assert diagonal_qubit_positions("rz", (0.2,), None) == [0]
+    assert diagonal_qubit_positions("swap", (), None) == []
+    # controlled-U built by hand: block diagonal in the control (bit 1)
+    cu = np.eye(4, dtype=complex)
+    cu[2:, 2:] = [[0, 1j], [1j, 0]]
+    assert diagonal_qubit_positions("unitary", (), cu) == [1]
+
+
+def test_cx_global_control_allowed_with_diag_free():
+    gates = [("cx", (2, 0), (), None, -1)]
+    ops = [("begin", 0b011), ("gate", 0, (2, 0)), ("end",)]
+    with pytest.raises(AssertionError):
+        oracle.run_plan(3, gates, ops, [0, 1, 2], 2)
+    psi = np.arange(8).astype(np.complex128)
+    got = oracle.run_plan(3, gates, ops, [0, 1, 2], 2, diag_free=True, psi=psi)
+    assert np.array_equal(got, oracle.apply_circuit(3, gates, psi))
