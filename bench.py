@@ -1,0 +1,260 @@
+"""Benchmark: cache-blocked gate application on one MI355X.
+
+Workload: the Quantum-Volume-style circuit at 33 qubits, complex128, in place
+(a 128 GiB state): depth 33, each layer a seeded random qubit permutation
+paired into Haar SU(4) gates (528 gates), seed 0.  One step applies the whole
+circuit through the blocked path (one kernel per section, every section one
+HBM read + one write of the state).  The per-gate path (one kernel per gate)
+runs once on the same circuit for the speedup and the parity check
+(1 - F between the two results, FP64 overlap on the device).
+
+Prints one JSON line.  `value` = algorithmic bytes of the blocked path
+(2 * 2^n * 16 B per section) / timed wall time, in GB/s.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "section_kernel_qv33_c128_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=33)
+    ap.add_argument("--dtype", choices=["c128", "c64"], default="c128")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--skip-pergate", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--chunk-bits", type=int, default=None)
+    ap.add_argument("--pinned", type=int, default=None)
+    ap.add_argument("--fusion", type=int, default=None)
+    ap.add_argument("--register-bits", type=int, default=None)
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("section_kernel.hip", "device.hpp", "qsv_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2102_02957_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
+    """The oracle as it stands, on a bounded sample of the same workload:
+    a 24-qubit Quantum-Volume circuit, gates applied until ~15 s have passed;
+    the per-gate-per-amplitude time is scaled to the 33-qubit circuit."""
+    import numpy as np
+    import oracle
+    from paper_2102_02957_amd import workloads as W
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = 1
+    ns = 24
+    gates = W.quantum_volume(ns, ns, seed)
+    psi = oracle.zero_state(ns)
+    t0 = time.perf_counter()
+    done = 0
+    for g in gates:
+        oracle.apply_gate(psi, ns, g)
+        done += 1
+        if time.perf_counter() - t0 > 15.0:
+            break
+    dt = time.perf_counter() - t0
+    per_gate_amp = dt / (done * float(1 << ns))
+    t_full = per_gate_amp * len(gates_target) * float(1 << n_target)
+    return {
+        "value": blocked_bytes / t_full / 1e9,
+        "unit": "GB/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": "NumPy oracle, %d of %d SU(4) gates of a %d-qubit QV circuit in %.1f s; "
+                  "time per gate per amplitude scaled x%d gates x2^%d amplitudes "
+                  "(extrapolated %.0f s for the %d-qubit circuit)"
+                  % (done, len(gates), ns, dt, len(gates_target), n_target, t_full, n_target),
+        "cpu": platform.processor() or platform.machine(),
+        "affinity_cores": len(os.sched_getaffinity(0)),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2102_02957_amd import binding as B
+    from paper_2102_02957_amd import workloads as W
+
+    n = args.n
+    dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64
+    tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
+    es = 16 if dt == B.QSV_C128 else 8
+    gates = W.quantum_volume(n, n, args.seed)
+    t0 = time.perf_counter()
+    plan = B.Plan(n, gates, dt, chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
+                  fusion_max_qubits=args.fusion, register_bits=args.register_bits)
+    t_plan = time.perf_counter() - t0
+    st = plan.stats()
+    S = st["n_sections"]
+    pass_bytes = 2.0 * (1 << n) * es
+    step_bytes = S * pass_bytes
+    log("planned n=%d gates=%d sections=%d phases=%d ops=%d in %.3f s"
+        % (n, len(gates), S, st["n_phases"], st["n_device_ops"], t_plan))
+
+    torch.cuda.init()
+    ctx = B.Context(dt)
+    A = torch.empty(1 << n, dtype=tdt, device="cuda")
+    ctx.init_basis(A, n, 0)
+    ctx.apply(plan, A)
+    torch.cuda.synchronize()
+    log("blocked apply #1 done")
+
+    parity = {}
+    pergate_ms = None
+    if not args.skip_pergate:
+        free, _ = torch.cuda.mem_get_info()
+        Bst = None
+        if free > A.numel() * es + (4 << 30):
+            Bst = torch.empty(1 << n, dtype=tdt, device="cuda")
+            ctx.init_basis(Bst, n, 0)
+        else:
+            Bst = A
+            log("not enough memory for a second state: per-gate path timed on the same buffer")
+        torch.cuda.synchronize()
+        ctx.timing(True)
+        t1 = time.perf_counter()
+        ctx.apply(plan, Bst, B.QSV_MODE_PER_GATE)
+        torch.cuda.synchronize()
+        pergate_ms = (time.perf_counter() - t1) * 1e3
+        pg_kernel_ms, pg_launches = ctx.timing_read(1, reset=True)
+        ctx.timing(False)
+        log("per-gate apply: %.1f ms (%d launches)" % (pergate_ms, pg_launches))
+        if Bst is not A:
+            ov = ctx.overlap(A, Bst, n).cpu().numpy()
+            fid = (ov[0] ** 2 + ov[1] ** 2) / (ov[2] * ov[3])
+            parity = {"one_minus_F_blocked_vs_pergate": float(1.0 - fid),
+                      "norm_error": float(abs(ov[2] - 1.0))}
+            log("parity: 1-F = %.3e, |norm-1| = %.3e" % (1.0 - fid, abs(ov[2] - 1.0)))
+            del Bst
+            torch.cuda.empty_cache()
+
+    for _ in range(max(0, args.warmup - 1)):
+        ctx.apply(plan, A)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(0, reset=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.apply(plan, A)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    sec_ms, sec_launches = ctx.timing_read(0, reset=True)
+    ctx.timing(False)
+    log("timed %d steps: %.1f ms/step" % (args.steps, wall * 1e3 / args.steps))
+
+    nrm = ctx.norm(A, n).item()
+    ms_per_step = wall * 1e3 / args.steps
+    value = step_bytes * args.steps / wall / 1e9
+    avg_launch_ms = sec_ms / max(1, sec_launches)
+    achieved = pass_bytes / (avg_launch_ms * 1e-3) / 1e9
+
+    # practical roofline: a plain streaming copy of 16 GiB through the same library
+    copy_gbs = None
+    try:
+        nc = 30 if dt == B.QSV_C128 else 31
+        X = torch.empty(1 << nc, dtype=tdt, device="cuda")
+        Y = torch.empty(1 << nc, dtype=tdt, device="cuda")
+        ctx.copy(Y, X, nc)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        for _ in range(5):
+            ctx.copy(Y, X, nc)
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2.0 * (1 << nc) * es / (time.perf_counter() - t2) / 1e9
+        del X, Y
+    except Exception as e:  # pragma: no cover
+        log("copy calibration skipped: %s" % e)
+
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as f:
+            prof = json.load(f)
+        if prof.get("kernel_source_hash") == kernel_source_hash() and prof.get("n") == n:
+            traffic = prof.get("bytes_per_launch")
+
+    rec = {
+        "metric": "blocked gate-apply GB/s (% HBM peak) vs per-gate path, 33q c128 at 1-F<1e-12",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if dt == B.QSV_C128 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "quantum-volume %dq depth %d, %s, seed %d, in place (%d GiB state)"
+                        % (n, n, args.dtype, args.seed, (1 << n) * es >> 30),
+            "gates": len(gates),
+            "sections": S,
+            "chunk_bits": st["chunk_bits"],
+            "register_bits": st["register_bits"],
+            "pinned_low_bits": st["pinned_low_bits"],
+            "fusion_max_qubits": st["fusion_max_qubits"],
+            "phases": st["n_phases"],
+            "plan_s": round(t_plan, 4),
+        },
+        "pct_hbm_peak": round(100.0 * value / HBM_PEAK_GBS, 2),
+        "gates_per_s": round(len(gates) * args.steps / wall, 2),
+        "pergate_ms": None if pergate_ms is None else round(pergate_ms, 1),
+        "speedup_vs_pergate": None if pergate_ms is None else round(pergate_ms / ms_per_step, 3),
+        "pergate_gbs_algorithmic": None if pergate_ms is None else round(
+            len(gates) * pass_bytes / (pergate_ms * 1e-3) / 1e9, 1),
+        "copy_kernel_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "final_norm": nrm,
+        "parity": parity,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_section<double,4>" if dt == B.QSV_C128 else "k_section<float,5>",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(avg_launch_ms, 3),
+            "launches": sec_launches,
+            "alu_tflops": round(st["section_flops"] * args.steps / (sec_ms * 1e-3) / 1e12, 2),
+        },
+    }
+    if not args.skip_cpu:
+        rec["cpu_baseline"] = cpu_baseline(n, gates, step_bytes, args.seed)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

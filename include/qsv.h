@@ -1,0 +1,237 @@
+/*
+ * qsv.h -- C ABI of the cache-blocked state-vector library (one AMD MI355X, gfx950).
+ *
+ * What is computed (Doi & Horii, arXiv:2102.02957):
+ *   A state of 2^n complex amplitudes (Sec. II-A), qubit k <-> bit k of the
+ *   amplitude index, evolved by a circuit, i.e. a sequence of gates (Sec. II-A,
+ *   Eq. (1) u3 and Eq. (2) CNOT).  The result is psi_out = U_G ... U_1 psi_in in
+ *   the original qubit order.
+ *
+ *   Blocked mode follows the paper's cache blocking (Sec. IV): the circuit is
+ *   transpiled into sections (begin_blocking ... end_blocking) each of which
+ *   acts only on the 2^c amplitudes of a chunk (Sec. III-B, IV-C), with
+ *   chunk_swap operations between sections choosing which qubits are local.
+ *   On one GPU the chunk is staged in on-chip memory (registers + LDS) instead
+ *   of GPU memory, so every section costs one read and one write of the state
+ *   in HBM instead of one per gate.  Per-gate mode applies one kernel per gate
+ *   (the baseline of Sec. V-A: every gate is one pass over the state).
+ *
+ * Conventions shared by every call:
+ *   - A state is a caller-owned, contiguous device array of 2^n amplitudes,
+ *     interleaved (re, im): float pairs for QSV_C64, double pairs for
+ *     QSV_C128, 256-byte aligned.  The library never frees or reallocates it.
+ *   - All device work is asynchronous on the caller's HIP stream `stream`
+ *     (hipStream_t passed as void*; NULL = the default stream).  Device faults
+ *     surface at the caller's next synchronisation.
+ *   - Every call returns a qsv_status; nothing throws across the ABI.  A
+ *     thread-local message for the last failure is returned by qsv_last_error().
+ *   - Arguments are validated eagerly on the host; an invalid call leaves all
+ *     buffers untouched and returns QSV_E_INVALID (or QSV_E_UNSUPPORTED).
+ */
+#ifndef QSV_INCLUDE_QSV_H_
+#define QSV_INCLUDE_QSV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QSV_OK = 0,
+    QSV_E_INVALID = -1,     /* bad argument (qubit out of range, duplicate, size) */
+    QSV_E_NOMEM = -2,       /* a library-owned workspace allocation failed */
+    QSV_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    QSV_E_UNSUPPORTED = -4, /* valid request this build does not handle */
+    QSV_E_NUMERIC = -5,     /* non-finite or zero norm where one is required */
+    QSV_E_STATE = -6        /* call out of order (e.g. destroyed object) */
+} qsv_status;
+
+typedef enum { QSV_C64 = 1, QSV_C128 = 2 } qsv_dtype;
+
+/* Gate kinds.  Qubit order of q[]:
+ *   one-qubit kinds: q[0]
+ *   QSV_CX: q[0] = control, q[1] = target   (Eq. (2): swap of the x_c=1 pairs)
+ *   QSV_CZ, QSV_CP, QSV_SWAP: q[0], q[1]
+ *   QSV_UNITARY: q[0..nq-1], q[0] the least significant bit of the matrix's
+ *                row/column index (local index = sum_j bit(q[j]) << j)
+ * Angles p[]:
+ *   QSV_U3: (theta, phi, lambda) of Eq. (1) (the paper's psi is OpenQASM's phi)
+ *   QSV_RX/RY/RZ: theta, exp(-i theta P / 2);  QSV_P: diag(1, e^{i p[0]});
+ *   QSV_CP: diag(1, 1, 1, e^{i p[0]}). */
+enum {
+    QSV_H = 1, QSV_X, QSV_Y, QSV_Z, QSV_S, QSV_SDG, QSV_T, QSV_TDG,
+    QSV_RX, QSV_RY, QSV_RZ, QSV_P, QSV_U3,
+    QSV_CX, QSV_CZ, QSV_CP, QSV_SWAP,
+    QSV_UNITARY
+};
+
+#define QSV_MAX_QUBITS 34       /* 2^34 amplitudes: 128 GiB complex64, 256 GiB complex128 */
+#define QSV_MAX_GATE_QUBITS 5
+
+typedef struct {
+    int32_t kind;
+    int32_t nq;                  /* number of qubits; must match the kind */
+    int32_t q[QSV_MAX_GATE_QUBITS];
+    int32_t param;               /* >= 0: p[0] is taken from params[param] at run time
+                                    (QSV_RX/RY/RZ/P only; qsv_adjoint_grad, qsv_apply_params) */
+    double p[3];
+    const double *m;             /* QSV_UNITARY: 2^nq x 2^nq complex, row-major, (re, im)
+                                    pairs, host memory, read during qsv_plan_blocks only */
+} qsv_gate;
+
+enum { QSV_SWAP_REMAP = 0, QSV_SWAP_MATERIALIZE = 1 };
+enum { QSV_MODE_BLOCKED = 0, QSV_MODE_PER_GATE = 1 };
+
+typedef struct {
+    int32_t chunk_bits;          /* c: qubits per chunk (Sec. III-B "nc"); 0 = default
+                                    (12 for QSV_C128, 13 for QSV_C64) */
+    int32_t pinned_low_bits;     /* L: physical bits 0..L-1 always local (coalescing); -1 = default */
+    int32_t fusion_max_qubits;   /* f: fuse consecutive in-section gates up to f qubits; 0/1 = off */
+    int32_t swap_mode;           /* QSV_SWAP_REMAP (chunk_swap = change of the chunk's bit set,
+                                    no data moves) or QSV_SWAP_MATERIALIZE (chunk_swap moves
+                                    amplitudes, Sec. IV-C Fig. "chunk_swap") */
+    int32_t diag_free;           /* 1: diagonal gates and CX controls need not be local (Sec. V-A:
+                                    QFT's diagonal gates need less exchange) */
+    int32_t register_bits;       /* r: amplitudes per GPU thread = 2^r; 0 = default */
+} qsv_options;
+
+/* Fill *opt with the defaults for dt. */
+qsv_status qsv_default_options(qsv_dtype dt, qsv_options *opt);
+
+/* ---- plans (host only; no GPU needed) ------------------------------------ */
+
+typedef struct qsv_plan qsv_plan;
+
+/* Cache-blocking transpile (Sec. IV-A, the transpiler listing): bit
+ * reordering, chunk qubit choice, chunk_swap insertion, section scan, then
+ * per-section register phases and gate fusion.  `g` is read during the call
+ * only.  n in [1, QSV_MAX_QUBITS].  The plan is immutable and may be shared
+ * between threads and contexts; destroy it only when no launch using it is in
+ * flight.  Errors: QSV_E_INVALID on a bad gate (kind, nq, qubit range,
+ * duplicates, missing matrix) or option. */
+qsv_status qsv_plan_blocks(const qsv_options *opt, qsv_dtype dt, int n,
+                           const qsv_gate *g, size_t ng, qsv_plan **plan);
+void qsv_plan_destroy(qsv_plan *plan);
+
+typedef struct {
+    int32_t n, dtype, chunk_bits, register_bits, pinned_low_bits, fusion_max_qubits;
+    int32_t swap_mode, diag_free;
+    int64_t n_gates;             /* gates in the circuit */
+    int64_t n_sections;          /* begin_blocking/end_blocking pairs */
+    int64_t n_chunk_swaps;       /* qubits moved into the chunk over the whole plan */
+    int64_t n_phases;            /* register phases over all sections */
+    int64_t n_device_ops;        /* in-section ops after fusion */
+    int64_t n_params;            /* 1 + largest gate param index (0 if none) */
+    double  section_flops;       /* FP operations of the blocked path (FMA = 2) */
+    int32_t final_perm[64];      /* logical qubit q sits at physical bit final_perm[q] after
+                                    the last section (identity in remap mode) */
+} qsv_plan_stats;
+qsv_status qsv_plan_get_stats(const qsv_plan *plan, qsv_plan_stats *out);
+
+/* Flat export of the transpiled circuit (Sec. IV-A output + Sec. IV-C ops):
+ *   QSV_OP_BEGIN: begin_blocking; `mask` = physical bits of the chunk
+ *   QSV_OP_END:   end_blocking
+ *   QSV_OP_CHUNK_SWAP: swap physical bits q[0], q[1] (materialise mode only)
+ *   QSV_OP_GATE:  circuit gate `gate` applied on physical qubits q[0..nq-1]
+ * Writes at most `cap` ops; *n_ops receives the total needed. */
+enum { QSV_OP_BEGIN = 1, QSV_OP_END = 2, QSV_OP_CHUNK_SWAP = 3, QSV_OP_GATE = 4 };
+typedef struct {
+    int32_t tag, gate, nq, q[QSV_MAX_GATE_QUBITS];
+    uint64_t mask;
+} qsv_op;
+qsv_status qsv_plan_export(const qsv_plan *plan, qsv_op *ops, size_t cap, size_t *n_ops);
+
+/* ---- device context ---------------------------------------------------- */
+
+typedef struct qsv_ctx qsv_ctx;
+
+/* Bind a context to HIP device `hip_device` for states of type dt.  The
+ * context owns small workspaces (uploaded plan tables, reduction partials),
+ * grown on demand.  Errors: QSV_E_HIP if the device is absent. */
+qsv_status qsv_create(qsv_ctx **ctx, int hip_device, qsv_dtype dt);
+void qsv_destroy(qsv_ctx *ctx);
+const char *qsv_last_error(void);
+
+/* state <- |basis> (Sec. IV-C: only one amplitude is 1, the rest 0). */
+qsv_status qsv_init_basis(qsv_ctx *ctx, void *state, int n, uint64_t basis, void *stream);
+
+/* state <- U_plan state, in place.  mode QSV_MODE_BLOCKED runs one kernel per
+ * section (plus one permutation pass per chunk_swap group in materialise
+ * mode, and a final reorder to the original qubit order); QSV_MODE_PER_GATE
+ * runs one kernel per circuit gate.  The plan's dtype must match the
+ * context's and plan n must equal n.  Plans with parameter-bound gates need
+ * qsv_apply_params. */
+qsv_status qsv_apply_circuit(qsv_ctx *ctx, const qsv_plan *plan, void *state, int n,
+                             int mode, void *stream);
+
+/* Checkpoint/resume: run sections [s0, s1) of a remap-mode blocked plan.  At
+ * every section boundary the state is the circuit prefix's state in the
+ * original order. */
+qsv_status qsv_apply_sections(qsv_ctx *ctx, const qsv_plan *plan, void *state, int n,
+                              int64_t s0, int64_t s1, void *stream);
+
+/* Blocked apply of a parameterised plan to `batch` states stored back to back
+ * (state b at states + b * 2^n amplitudes), parameters params_dev[b * P + p]
+ * (device, double), P = stats.n_params. */
+qsv_status qsv_apply_params(qsv_ctx *ctx, const qsv_plan *plan, void *states, int n, int batch,
+                            const double *params_dev, void *stream);
+
+/* ---- FP64 reductions (deterministic; device outputs) ------------------- */
+
+typedef struct { double coeff; uint64_t zmask; } qsv_zterm;  /* coeff * prod_{i in zmask} Z_i */
+
+/* out_dev[0] = <psi|psi> */
+qsv_status qsv_norm(qsv_ctx *ctx, const void *state, int n, double *out_dev, void *stream);
+/* out_dev[0..3] = Re<a|b>, Im<a|b>, <a|a>, <b|b> */
+qsv_status qsv_overlap(qsv_ctx *ctx, const void *a, const void *b, int n, double *out_dev,
+                       void *stream);
+/* out_dev[0] = sum_x |a_x|^2 sum_t coeff_t (-1)^popcount(x & zmask_t)  (terms: host array) */
+qsv_status qsv_expval(qsv_ctx *ctx, const void *state, int n, const qsv_zterm *terms,
+                      size_t n_terms, double *out_dev, void *stream);
+/* Divide the state by sqrt(<psi|psi>) (computed in FP64); norm_out_dev[0] = <psi|psi>
+ * before scaling.  A zero or non-finite norm leaves the state unscaled and sets
+ * norm_out_dev[0] to it; the caller checks it. */
+qsv_status qsv_normalize(qsv_ctx *ctx, void *state, int n, double *norm_out_dev, void *stream);
+/* dst <- src (2^n amplitudes): a plain streaming copy. */
+qsv_status qsv_copy(qsv_ctx *ctx, void *dst, const void *src, int n, void *stream);
+
+/* ---- adjoint gradient -------------------------------------------------- */
+
+/* E_b = <psi_b|H|psi_b>, grad_b[p] = dE_b / dtheta_p for psi_b = U(theta_b)|0>, H = sum of
+ * Z-strings, batch states.  psi_dev and lambda_dev are caller workspaces of batch * 2^n
+ * amplitudes each (psi_dev holds the final states on return).  energy_dev[batch],
+ * grad_dev[batch * P] (device, double; P = stats.n_params).  The reverse sweep follows
+ * the blocked plan backwards, one kernel per section holding both chunks. */
+qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm *terms,
+                            size_t n_terms, const double *params_dev, int batch,
+                            void *psi_dev, void *lambda_dev, double *energy_dev,
+                            double *grad_dev, void *stream);
+
+/* ---- batched trajectories ---------------------------------------------- */
+
+/* Run `count` independent circuits, each on its own state of n_b qubits stored
+ * at states + offsets[b] amplitudes (offsets: host array, 256-byte aligned
+ * starts), in one persistent launch: init |0>, every section of plans[b],
+ * FP64 norm, renormalise.  norms_dev[b] receives <psi_b|psi_b> before the
+ * renormalisation.  Every plan must have n_b <= its chunk_bits... or any size:
+ * multi-section plans are ordered by per-state section counters. */
+qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *const *plans,
+                         const uint64_t *offsets, void *states, double *norms_dev,
+                         void *stream);
+
+/* ---- timing (in-library HIP events around each launch) ------------------ */
+
+/* When enabled, every section / per-gate launch is bracketed by HIP events on the
+ * launch stream; qsv_timing_read returns the summed kernel milliseconds and launch
+ * counts since the last reset for kernel class `which`
+ * (0 = section kernels, 1 = per-gate kernels).  Reading synchronises the stream. */
+qsv_status qsv_timing_enable(qsv_ctx *ctx, int enable);
+qsv_status qsv_timing_read(qsv_ctx *ctx, int which, double *total_ms, int64_t *launches,
+                           int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSV_INCLUDE_QSV_H_ */

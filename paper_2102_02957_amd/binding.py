@@ -1,0 +1,337 @@
+"""ctypes binding of the C ABI in include/qsv.h (argument marshalling only).
+
+Every computation runs in libqsv.so's HIP kernels; this module converts gate
+lists to ``qsv_gate`` arrays, passes device pointers of torch tensors and the
+current HIP stream, and turns status codes into exceptions.  If the shared
+library is missing the import of ``lib()`` raises: there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqsv.so")
+
+QSV_C64, QSV_C128 = 1, 2
+QSV_SWAP_REMAP, QSV_SWAP_MATERIALIZE = 0, 1
+QSV_MODE_BLOCKED, QSV_MODE_PER_GATE = 0, 1
+QSV_OP_BEGIN, QSV_OP_END, QSV_OP_CHUNK_SWAP, QSV_OP_GATE = 1, 2, 3, 4
+
+KINDS = {k: i + 1 for i, k in enumerate(
+    ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "rx", "ry", "rz", "p", "u3",
+     "cx", "cz", "cp", "swap", "unitary"])}
+
+STATUS = {0: "QSV_OK", -1: "QSV_E_INVALID", -2: "QSV_E_NOMEM", -3: "QSV_E_HIP",
+          -4: "QSV_E_UNSUPPORTED", -5: "QSV_E_NUMERIC", -6: "QSV_E_STATE"}
+
+
+class QsvError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("nq", ctypes.c_int32), ("q", ctypes.c_int32 * 5),
+                ("param", ctypes.c_int32), ("p", ctypes.c_double * 3),
+                ("m", ctypes.POINTER(ctypes.c_double))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("chunk_bits", ctypes.c_int32), ("pinned_low_bits", ctypes.c_int32),
+                ("fusion_max_qubits", ctypes.c_int32), ("swap_mode", ctypes.c_int32),
+                ("diag_free", ctypes.c_int32), ("register_bits", ctypes.c_int32)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("dtype", ctypes.c_int32), ("chunk_bits", ctypes.c_int32),
+                ("register_bits", ctypes.c_int32), ("pinned_low_bits", ctypes.c_int32),
+                ("fusion_max_qubits", ctypes.c_int32), ("swap_mode", ctypes.c_int32),
+                ("diag_free", ctypes.c_int32), ("n_gates", ctypes.c_int64),
+                ("n_sections", ctypes.c_int64), ("n_chunk_swaps", ctypes.c_int64),
+                ("n_phases", ctypes.c_int64), ("n_device_ops", ctypes.c_int64),
+                ("n_params", ctypes.c_int64), ("section_flops", ctypes.c_double),
+                ("final_perm", ctypes.c_int32 * 64)]
+
+
+class Op(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_int32), ("gate", ctypes.c_int32), ("nq", ctypes.c_int32),
+                ("q", ctypes.c_int32 * 5), ("mask", ctypes.c_uint64)]
+
+
+class ZTerm(ctypes.Structure):
+    _fields_ = [("coeff", ctypes.c_double), ("zmask", ctypes.c_uint64)]
+
+
+EXPORTED = [
+    "qsv_default_options", "qsv_plan_blocks", "qsv_plan_destroy", "qsv_plan_get_stats",
+    "qsv_plan_export", "qsv_create", "qsv_destroy", "qsv_last_error", "qsv_init_basis",
+    "qsv_apply_circuit", "qsv_apply_sections", "qsv_apply_params", "qsv_norm", "qsv_overlap",
+    "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
+    "qsv_timing_enable", "qsv_timing_read",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libqsv.so (built in-tree by ``paper_2102_02957_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqsv.so not built: run `python -m paper_2102_02957_amd.build` "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, U64, SZ, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+    sigs = {
+        "qsv_default_options": (I, [I, ctypes.POINTER(Options)]),
+        "qsv_plan_blocks": (I, [ctypes.POINTER(Options), I, I, ctypes.POINTER(Gate), SZ,
+                                ctypes.POINTER(P)]),
+        "qsv_plan_destroy": (None, [P]),
+        "qsv_plan_get_stats": (I, [P, ctypes.POINTER(PlanStats)]),
+        "qsv_plan_export": (I, [P, ctypes.POINTER(Op), SZ, ctypes.POINTER(SZ)]),
+        "qsv_create": (I, [ctypes.POINTER(P), I, I]),
+        "qsv_destroy": (None, [P]),
+        "qsv_last_error": (ctypes.c_char_p, []),
+        "qsv_init_basis": (I, [P, P, I, U64, P]),
+        "qsv_apply_circuit": (I, [P, P, P, I, I, P]),
+        "qsv_apply_sections": (I, [P, P, P, I, ctypes.c_int64, ctypes.c_int64, P]),
+        "qsv_apply_params": (I, [P, P, P, I, I, P, P]),
+        "qsv_norm": (I, [P, P, I, P, P]),
+        "qsv_overlap": (I, [P, P, P, I, P, P]),
+        "qsv_expval": (I, [P, P, I, ctypes.POINTER(ZTerm), SZ, P, P]),
+        "qsv_normalize": (I, [P, P, I, P, P]),
+        "qsv_copy": (I, [P, P, P, I, P]),
+        "qsv_adjoint_grad": (I, [P, P, ctypes.POINTER(ZTerm), SZ, P, I, P, P, P, P, P]),
+        "qsv_batch_run": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(U64), P, P, P]),
+        "qsv_timing_enable": (I, [P, I]),
+        "qsv_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), I]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise QsvError(rc, lib().qsv_last_error().decode(errors="replace"))
+
+
+def default_options(dtype):
+    o = Options()
+    _check(lib().qsv_default_options(dtype, ctypes.byref(o)))
+    return o
+
+
+def make_options(dtype, **kw):
+    o = default_options(dtype)
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if not hasattr(o, k):
+            raise TypeError("unknown option %r" % k)
+        setattr(o, k, int(v))
+    return o
+
+
+def gates_to_c(gates):
+    """Convert gate tuples (kind, qubits, params, matrix, pidx) to a qsv_gate array.
+    Returns (array, keepalive)."""
+    arr = (Gate * max(1, len(gates)))()
+    keep = []
+    for i, g in enumerate(gates):
+        kind, qubits, params, matrix, pidx = g[0], g[1], g[2], g[3], (g[4] if len(g) > 4 else -1)
+        c = arr[i]
+        if kind not in KINDS:
+            raise ValueError("unknown gate kind %r" % (kind,))
+        c.kind = KINDS[kind]
+        c.nq = len(qubits)
+        for j, q in enumerate(qubits):
+            c.q[j] = int(q)
+        c.param = -1 if pidx is None else int(pidx)
+        for j, v in enumerate(params):
+            c.p[j] = float(v)
+        if kind == "unitary" and matrix is not None:
+            m = np.ascontiguousarray(np.asarray(matrix, dtype=np.complex128))
+            buf = m.view(np.float64)
+            keep.append(buf)
+            c.m = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            c.m = None
+    return arr, keep
+
+
+class Plan:
+    """A cache-blocked plan (host object; see qsv_plan_blocks)."""
+
+    def __init__(self, n, gates, dtype=QSV_C128, **options):
+        self.n = int(n)
+        self.dtype = dtype
+        self.gates = list(gates)
+        opt = make_options(dtype, **options)
+        arr, keep = gates_to_c(self.gates)
+        h = ctypes.c_void_p()
+        _check(lib().qsv_plan_blocks(ctypes.byref(opt), dtype, self.n, arr, len(self.gates),
+                                     ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def stats(self):
+        s = PlanStats()
+        _check(lib().qsv_plan_get_stats(self._h, ctypes.byref(s)))
+        d = {f: getattr(s, f) for f, _ in PlanStats._fields_ if f != "final_perm"}
+        d["final_perm"] = [s.final_perm[q] for q in range(self.n)]
+        return d
+
+    def export(self):
+        """The transpiled op list in the oracle's plan format."""
+        need = ctypes.c_size_t()
+        _check(lib().qsv_plan_export(self._h, None, 0, ctypes.byref(need)))
+        ops = (Op * max(1, need.value))()
+        _check(lib().qsv_plan_export(self._h, ops, need.value, ctypes.byref(need)))
+        out = []
+        for o in ops[:need.value]:
+            if o.tag == QSV_OP_BEGIN:
+                out.append(("begin", int(o.mask)))
+            elif o.tag == QSV_OP_END:
+                out.append(("end",))
+            elif o.tag == QSV_OP_CHUNK_SWAP:
+                out.append(("swap", o.q[0], o.q[1]))
+            else:
+                out.append(("gate", o.gate, tuple(o.q[j] for j in range(o.nq))))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qsv_plan_destroy(h)
+            self._h = None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def dtype_of(t):
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return QSV_C128
+    if t.dtype == torch.complex64:
+        return QSV_C64
+    raise TypeError("state must be complex64 or complex128, got %s" % t.dtype)
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check_state(t, n, batch=1):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("state must be a contiguous device tensor")
+    if t.numel() != (batch << n):
+        raise ValueError("state must hold %d x 2^%d amplitudes" % (batch, n))
+
+
+class Context:
+    """A device context (qsv_create) for one dtype."""
+
+    def __init__(self, dtype=QSV_C128, device=0):
+        self.dtype = dtype
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().qsv_create(ctypes.byref(h), int(device), int(dtype)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qsv_destroy(h)
+            self._h = None
+
+    def init_basis(self, state, n, basis=0, stream=None):
+        _check_state(state, n)
+        _check(lib().qsv_init_basis(self._h, _ptr(state), n, int(basis), _stream(stream)))
+
+    def apply(self, plan, state, mode=QSV_MODE_BLOCKED, stream=None):
+        _check_state(state, plan.n)
+        _check(lib().qsv_apply_circuit(self._h, plan.handle, _ptr(state), plan.n, int(mode),
+                                       _stream(stream)))
+
+    def apply_sections(self, plan, state, s0, s1, stream=None):
+        _check_state(state, plan.n)
+        _check(lib().qsv_apply_sections(self._h, plan.handle, _ptr(state), plan.n, int(s0),
+                                        int(s1), _stream(stream)))
+
+    def apply_params(self, plan, states, params, stream=None):
+        batch = params.shape[0]
+        _check_state(states, plan.n, batch)
+        if params.dtype != _torch().float64 or not params.is_cuda or not params.is_contiguous():
+            raise ValueError("params must be a contiguous float64 device tensor")
+        _check(lib().qsv_apply_params(self._h, plan.handle, _ptr(states), plan.n, int(batch),
+                                      _ptr(params), _stream(stream)))
+
+    def norm(self, state, n, out=None, stream=None):
+        torch = _torch()
+        _check_state(state, n)
+        out = torch.empty(1, dtype=torch.float64, device=state.device) if out is None else out
+        _check(lib().qsv_norm(self._h, _ptr(state), n, _ptr(out), _stream(stream)))
+        return out
+
+    def overlap(self, a, b, n, out=None, stream=None):
+        torch = _torch()
+        _check_state(a, n)
+        _check_state(b, n)
+        out = torch.empty(4, dtype=torch.float64, device=a.device) if out is None else out
+        _check(lib().qsv_overlap(self._h, _ptr(a), _ptr(b), n, _ptr(out), _stream(stream)))
+        return out
+
+    def expval(self, state, n, terms, out=None, stream=None):
+        torch = _torch()
+        _check_state(state, n)
+        arr = (ZTerm * len(terms))()
+        for i, (c, m) in enumerate(terms):
+            arr[i].coeff = float(c)
+            arr[i].zmask = int(m)
+        out = torch.empty(1, dtype=torch.float64, device=state.device) if out is None else out
+        _check(lib().qsv_expval(self._h, _ptr(state), n, arr, len(terms), _ptr(out),
+                                _stream(stream)))
+        return out
+
+    def normalize(self, state, n, out=None, stream=None):
+        torch = _torch()
+        _check_state(state, n)
+        out = torch.empty(1, dtype=torch.float64, device=state.device) if out is None else out
+        _check(lib().qsv_normalize(self._h, _ptr(state), n, _ptr(out), _stream(stream)))
+        return out
+
+    def copy(self, dst, src, n, stream=None):
+        _check_state(dst, n)
+        _check_state(src, n)
+        _check(lib().qsv_copy(self._h, _ptr(dst), _ptr(src), n, _stream(stream)))
+
+    def timing(self, enable):
+        _check(lib().qsv_timing_enable(self._h, 1 if enable else 0))
+
+    def timing_read(self, which=0, reset=True):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check(lib().qsv_timing_read(self._h, int(which), ctypes.byref(ms), ctypes.byref(cnt),
+                                     1 if reset else 0))
+        return ms.value, cnt.value

@@ -1,0 +1,55 @@
+// Device-side helpers and host-callable launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "qsv_internal.hpp"
+
+namespace qsv {
+
+// amplitude type: (re, im) interleaved, aligned to its size so that one amplitude
+// is one 8- or 16-byte memory access.  A plain struct (not HIP's vector types)
+// so that arrays of it are promoted to registers.
+template <typename T> struct alignas(2 * sizeof(T)) Cplx {
+    T x, y;
+};
+template <typename T> struct Amp { using V = Cplx<T>; };
+
+struct DevPlanView {           // device pointers of one uploaded plan
+    const DevSection *secs;
+    const DevPhase *phases;
+    const DevOp *ops;
+    const void *mats;          // V[] in the context's dtype
+    const PgOp *pg;
+};
+
+// ---- launchers (kernels.hip) ----------------------------------------------
+
+// One section of a blocked plan over `batch` states (state b at state + b * 2^n).
+// lds_bytes == 0 when the section has a single phase.
+// kmax: widest dense op in the plan (selects the kernel instance).
+hipError_t launch_section(qsv_dtype dt, int r, int kmax, void *state, int n, int batch,
+                          DevPlanView pv, int sec, int c, size_t lds_bytes, const double *params,
+                          int n_params, hipStream_t s);
+// `hmats`: the plan's FP64 host table (diagonal entries are passed by value);
+// `dmats`: its device copy in the state's dtype (dense matrices are read there).
+hipError_t launch_pergate_host(qsv_dtype dt, void *state, int n, const PgOp &op, const cd *hmats,
+                               const void *dmats, hipStream_t s);
+hipError_t launch_fill_basis(qsv_dtype dt, void *state, int n, int batch, uint64_t basis,
+                             hipStream_t s);
+hipError_t launch_copy(qsv_dtype dt, void *dst, const void *src, int n, hipStream_t s);
+hipError_t launch_swap_bits(qsv_dtype dt, void *state, int n, const uint8_t *pa,
+                            const uint8_t *pb, int npairs, hipStream_t s);
+
+// FP64 reductions: partials (double, `nblk` * width) then a single-block final sum.
+// kind: 0 norm (width 1), 1 overlap (width 4), 2 Z-string expval (width 1)
+hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, int n, int batch,
+                         const qsv_zterm *terms_dev, int n_terms, double *partials, int nblk,
+                         double *out, hipStream_t s);
+hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,
+                                hipStream_t s);
+int reduce_blocks(int n);
+
+}  // namespace qsv

@@ -1,0 +1,817 @@
+// Host planner: the cache-blocking transpiler of Sec. IV-A and its lowering to
+// device tables.
+//
+// Steps (all host, deterministic, no GPU):
+//   1. validate the gates and build FP64 matrices (Eq. (1), Eq. (2), textbook);
+//   2. blocking (the transpiler listing of Sec. IV-A, made precise):
+//        repeat until no gate remains:
+//          choose the chunk's qubit set (c qubits) from the remaining gates;
+//          emit chunk_swaps (materialise mode) or just switch the chunk's bit set
+//          (remap mode: nothing moves, the next section gathers other bits);
+//          scan the remaining gates in order: a gate whose qubits are all in
+//          the chunk and none of whose qubits is blocked joins the section;
+//          otherwise all its qubits become blocked and it waits for the next
+//          round (gates on disjoint qubits commute, so this only reorders
+//          commuting gates; Sec. IV-A);
+//      readings where the listing is loose: the chunk holds c qubits (not c-1),
+//      a deferred gate blocks all of its qubits, and the first remaining gate
+//      is always admitted so that every section makes progress;
+//   3. per section, the same greedy step one level down: register phases
+//      (which r chunk qubits sit in each thread's registers), then fusion of
+//      consecutive register gates into dense matrices of at most f qubits;
+//   4. the per-gate op list (one kernel per gate, the unblocked baseline).
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+
+#include "qsv_internal.hpp"
+
+namespace qsv {
+
+static inline int popc(uint64_t x) { return __builtin_popcountll(x); }
+static inline uint64_t bit(int q) { return 1ull << q; }
+
+void default_options(qsv_dtype dt, qsv_options &o) {
+    std::memset(&o, 0, sizeof(o));
+    o.chunk_bits = dt == QSV_C64 ? 13 : 12;
+    o.pinned_low_bits = dt == QSV_C64 ? 4 : 3;
+    o.fusion_max_qubits = 2;
+    o.swap_mode = QSV_SWAP_REMAP;
+    o.diag_free = 1;
+    o.register_bits = dt == QSV_C64 ? 5 : 4;
+}
+
+// ---------------------------------------------------------------------------
+// gate classification
+
+namespace {
+
+bool is_param_rot(const GateRec &g) { return g.param >= 0; }
+
+// qubits that must be inside the chunk for the gate to run in a section
+uint64_t need_local(const GateRec &g, bool diag_free) {
+    if (g.is_swap) return g.qmask;
+    if (diag_free) {
+        if (g.diagonal) return 0;
+        if (g.kind == QSV_CX) return bit(g.q[1]);
+    }
+    return g.qmask;
+}
+
+// qubits that must sit in register positions for the gate to run in a phase
+uint64_t need_reg(const GateRec &g) {
+    if (g.is_swap || g.diagonal) return 0;
+    if (g.kind == QSV_CX) return bit(g.q[1]);
+    return g.qmask;
+}
+
+// ---------------------------------------------------------------------------
+// chunk choice (remap mode): several greedy candidates, keep the one whose
+// section admits the most gates.
+
+struct Blocker {
+    const std::vector<GateRec> &G;
+    bool diag_free;
+};
+
+uint64_t choose_inorder(const Blocker &B, const std::vector<int> &rem, uint64_t start, int cap,
+                        int min_arity) {
+    uint64_t chosen = start, blocked = 0;
+    for (int idx : rem) {
+        const GateRec &g = B.G[idx];
+        uint64_t nm = need_local(g, B.diag_free);
+        if (g.qmask & blocked) {
+            blocked |= g.qmask;
+            continue;
+        }
+        if (popc(nm) < min_arity) {
+            // the first pass of the listing looks at multi-qubit gates only; a
+            // 1-qubit gate on a qubit not yet chosen would be deferred by the
+            // scan and so blocks its qubit
+            if ((nm & ~chosen) != 0) blocked |= g.qmask;
+            continue;
+        }
+        if (popc(chosen | nm) <= cap)
+            chosen |= nm;
+        else
+            blocked |= g.qmask;
+    }
+    return chosen;
+}
+
+int scan_count(const Blocker &B, const std::vector<int> &rem, uint64_t local) {
+    uint64_t blocked = 0;
+    int cnt = 0;
+    for (int idx : rem) {
+        const GateRec &g = B.G[idx];
+        if (!(g.qmask & blocked) && !(need_local(g, B.diag_free) & ~local))
+            ++cnt;
+        else
+            blocked |= g.qmask;
+    }
+    return cnt;
+}
+
+uint64_t fill_low(uint64_t chosen, int cap, int n) {
+    for (int q = 0; q < n && popc(chosen) < cap; ++q) chosen |= bit(q);
+    return chosen;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<GateRec> &out,
+                               int64_t &n_params, std::string &err) {
+    out.clear();
+    out.reserve(ng);
+    n_params = 0;
+    for (size_t i = 0; i < ng; ++i) {
+        const qsv_gate &s = g[i];
+        GateRec r;
+        r.kind = s.kind;
+        int nq = 0;
+        if (!gate_arity(s.kind, nq)) {
+            err = "gate " + std::to_string(i) + ": unknown kind " + std::to_string(s.kind);
+            return false;
+        }
+        if (nq < 0) {
+            if (s.nq < 1 || s.nq > QSV_MAX_GATE_QUBITS) {
+                err = "gate " + std::to_string(i) + ": unitary arity must be 1..5";
+                return false;
+            }
+            nq = s.nq;
+        }
+        if (s.nq != nq) {
+            err = "gate " + std::to_string(i) + ": nq does not match its kind";
+            return false;
+        }
+        r.nq = nq;
+        for (int j = 0; j < nq; ++j) {
+            if (s.q[j] < 0 || s.q[j] >= n) {
+                err = "gate " + std::to_string(i) + ": qubit out of range";
+                return false;
+            }
+            if (r.qmask & bit(s.q[j])) {
+                err = "gate " + std::to_string(i) + ": repeated qubit";
+                return false;
+            }
+            r.q[j] = s.q[j];
+            r.qmask |= bit(s.q[j]);
+        }
+        for (int j = 0; j < 3; ++j) r.p[j] = s.p[j];
+        if (!std::isfinite(r.p[0]) || !std::isfinite(r.p[1]) || !std::isfinite(r.p[2])) {
+            err = "gate " + std::to_string(i) + ": non-finite angle";
+            return false;
+        }
+        r.param = s.param;
+        if (s.param >= 0) {
+            if (s.kind != QSV_RX && s.kind != QSV_RY && s.kind != QSV_RZ && s.kind != QSV_P) {
+                err = "gate " + std::to_string(i) + ": only rx/ry/rz/p take a bound parameter";
+                return false;
+            }
+            n_params = std::max<int64_t>(n_params, (int64_t)s.param + 1);
+        }
+        r.diagonal = kind_is_diagonal(s.kind);
+        r.is_swap = s.kind == QSV_SWAP;
+        if (s.kind == QSV_UNITARY) {
+            if (!s.m) {
+                err = "gate " + std::to_string(i) + ": unitary without matrix";
+                return false;
+            }
+            size_t d = size_t(1) << nq;
+            r.m.resize(d * d);
+            for (size_t e = 0; e < d * d; ++e) {
+                r.m[e] = cd(s.m[2 * e], s.m[2 * e + 1]);
+                if (!std::isfinite(s.m[2 * e]) || !std::isfinite(s.m[2 * e + 1])) {
+                    err = "gate " + std::to_string(i) + ": non-finite matrix entry";
+                    return false;
+                }
+            }
+            bool diag = true;
+            for (size_t a = 0; a < d && diag; ++a)
+                for (size_t b = 0; b < d; ++b)
+                    if (a != b && r.m[a * d + b] != cd(0.0, 0.0)) {
+                        diag = false;
+                        break;
+                    }
+            r.diagonal = diag;
+        } else {
+            named_matrix(s.kind, r.p, r.m);
+        }
+        out.push_back(std::move(r));
+    }
+    return true;
+}
+
+// Permute a k-qubit matrix from gate order (local bit j = gate qubit j) into the
+// order in which local bit j is the j-th smallest of `keys` (keys[j] = sort key
+// of gate qubit j).  Returns the sorted keys' permutation in `order`.
+static std::vector<cd> sorted_matrix(const std::vector<cd> &m, int k, const int *keys,
+                                     std::vector<int> &order) {
+    order.resize(k);
+    for (int j = 0; j < k; ++j) order[j] = j;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+    // new local bit t holds gate bit order[t]
+    size_t d = size_t(1) << k;
+    auto remap = [&](size_t x) {
+        size_t y = 0;
+        for (int t = 0; t < k; ++t) y |= ((x >> order[t]) & 1) << t;
+        return y;
+    };
+    std::vector<cd> out(d * d);
+    for (size_t a = 0; a < d; ++a)
+        for (size_t b = 0; b < d; ++b) out[remap(a) * d + remap(b)] = m[a * d + b];
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// blocking
+
+static void block_circuit(Plan &P) {
+    const int n = P.n;
+    const int c = P.c;
+    const bool diag_free = P.opt.diag_free != 0;
+    const bool materialise = P.opt.swap_mode == QSV_SWAP_MATERIALIZE;
+    const int L = materialise ? 0 : P.opt.pinned_low_bits;
+    Blocker B{P.gates, diag_free};
+
+    std::vector<int> rem(P.gates.size());
+    for (size_t i = 0; i < rem.size(); ++i) rem[i] = (int)i;
+
+    std::vector<int> layout(n), inv(n);  // logical -> physical, physical -> logical
+    for (int q = 0; q < n; ++q) layout[q] = inv[q] = q;
+    const uint64_t pinned = (L > 0) ? ((1ull << L) - 1) : 0;
+
+    P.sections.clear();
+    P.chunk_swaps = 0;
+    uint64_t prev_local_logical = 0;
+    bool first = true;
+    while (!rem.empty()) {
+        // candidate chunk sets; the first remaining gate is never blocked, so
+        // each candidate admits it
+        uint64_t start = 0;
+        if (!materialise) start = pinned;  // remap: logical == physical, low bits pinned
+        uint64_t cands[3];
+        cands[0] = choose_inorder(B, rem, start, c, 1);
+        cands[1] = choose_inorder(B, rem, start, c, 2);
+        {
+            // paper order: multi-qubit gates choose first, then 1-qubit gates fill
+            uint64_t s = cands[1];
+            cands[2] = choose_inorder(B, rem, s, c, 1);
+        }
+        uint64_t best = 0;
+        int best_cnt = -1;
+        for (uint64_t cand : cands) {
+            uint64_t full = cand;
+            if (materialise) {
+                // fill with qubits already in the chunk (no swap needed)
+                for (int p = 0; p < c && popc(full) < c; ++p) full |= bit(inv[p]);
+            }
+            full = fill_low(full, c, n);
+            int cnt = scan_count(B, rem, full);
+            if (cnt > best_cnt) {
+                best_cnt = cnt;
+                best = full;
+            }
+        }
+        uint64_t local = best;  // logical qubits in the chunk
+
+        HostSection S;
+        if (materialise) {
+            // chunk_swaps: every chosen qubit outside physical [0, c) trades places with
+            // an unchosen qubit inside, the one used farthest in the future (ties: highest slot)
+            std::vector<int> next_use(n, INT32_MAX);
+            for (size_t t = rem.size(); t-- > 0;) {
+                const GateRec &g = P.gates[rem[t]];
+                for (int j = 0; j < g.nq; ++j) next_use[g.q[j]] = (int)t;
+            }
+            for (int q = 0; q < n; ++q) {
+                if (!((local >> q) & 1) || layout[q] < c) continue;
+                int victim_slot = -1;
+                for (int p = 0; p < c; ++p) {
+                    int lq = inv[p];
+                    if ((local >> lq) & 1) continue;
+                    if (victim_slot < 0 || next_use[lq] > next_use[inv[victim_slot]] ||
+                        (next_use[lq] == next_use[inv[victim_slot]] && p > victim_slot))
+                        victim_slot = p;
+                }
+                int a = victim_slot, b = layout[q];
+                int qa = inv[a];
+                S.swaps_before.push_back({a, b});
+                layout[q] = a;
+                layout[qa] = b;
+                inv[a] = q;
+                inv[b] = qa;
+                ++P.chunk_swaps;
+            }
+        } else if (!first) {
+            P.chunk_swaps += popc(local & ~prev_local_logical);
+        }
+        uint64_t phys_mask = 0;
+        for (int q = 0; q < n; ++q)
+            if ((local >> q) & 1) phys_mask |= bit(layout[q]);
+        for (int p = 0; p < n; ++p)
+            if ((phys_mask >> p) & 1) S.phys_local.push_back(p);
+        S.layout_at = layout;
+
+        std::vector<int> next;
+        uint64_t blocked = 0;
+        for (int idx : rem) {
+            const GateRec &g = P.gates[idx];
+            if (!(g.qmask & blocked) && !(need_local(g, diag_free) & ~local))
+                S.gates.push_back(idx);
+            else {
+                blocked |= g.qmask;
+                next.push_back(idx);
+            }
+        }
+        P.sections.push_back(std::move(S));
+        rem.swap(next);
+        prev_local_logical = local;
+        first = false;
+    }
+    if (P.sections.empty()) {
+        // an empty circuit still has one (identity) section so that the apply is well defined
+        HostSection S;
+        for (int p = 0; p < std::min(c, n); ++p) S.phys_local.push_back(p);
+        S.layout_at = layout;
+        P.sections.push_back(S);
+    }
+    P.final_perm = layout;
+    // restore swaps (materialise): bring every logical qubit home with transpositions
+    P.restore_swaps.clear();
+    if (materialise) {
+        std::vector<int> lay = layout, iv = inv;
+        for (int q = 0; q < n; ++q) {
+            if (lay[q] == q) continue;
+            int a = q, b = lay[q];  // physical a holds iv[a]; move q from b to a
+            int qa = iv[a];
+            P.restore_swaps.push_back({std::min(a, b), std::max(a, b)});
+            lay[q] = a;
+            lay[qa] = b;
+            iv[a] = q;
+            iv[b] = qa;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// register phases + fusion for one section
+
+namespace {
+
+struct POp {                      // op before encoding, on data positions
+    DevOp op;
+    std::vector<cd> m;            // dense matrix / diagonal table (FP64)
+    bool fusable = false;         // dense-able on register positions only
+    uint32_t regmask = 0;         // register positions it reads/writes (fusable ops)
+};
+
+// Embed op `o` (fusable) as a dense matrix over the positions in `pos` (ascending).
+std::vector<cd> embed(const POp &o, const std::vector<int> &pos) {
+    int k = (int)pos.size();
+    size_t d = size_t(1) << k;
+    auto idx_of = [&](int p) {
+        for (int t = 0; t < k; ++t)
+            if (pos[t] == p) return t;
+        return -1;
+    };
+    std::vector<cd> E(d * d, cd(0, 0));
+    const DevOp &op = o.op;
+    for (size_t x = 0; x < d; ++x) {
+        // column x: the image of basis state x
+        if (op.type == OP_DENSE) {
+            int kk = op.k;
+            int t[5];
+            for (int j = 0; j < kk; ++j) t[j] = idx_of(op.a[j]);
+            size_t sub = 0;
+            for (int j = 0; j < kk; ++j) sub |= ((x >> t[j]) & 1) << j;
+            size_t rest = x;
+            for (int j = 0; j < kk; ++j) rest &= ~(size_t(1) << t[j]);
+            size_t dk = size_t(1) << kk;
+            for (size_t row = 0; row < dk; ++row) {
+                size_t y = rest;
+                for (int j = 0; j < kk; ++j) y |= ((row >> j) & 1) << t[j];
+                E[y * d + x] += o.m[row * dk + sub];
+            }
+        } else if (op.type == OP_XREG) {
+            int t = idx_of(op.a[0]);
+            E[(x ^ (size_t(1) << t)) * d + x] = 1.0;
+        } else if (op.type == OP_CX) {
+            int t = idx_of(op.a[0]), cc = idx_of(op.a[1]);
+            size_t y = ((x >> cc) & 1) ? (x ^ (size_t(1) << t)) : x;
+            E[y * d + x] = 1.0;
+        } else if (op.type == OP_DIAG) {
+            size_t sub = 0;
+            for (int j = 0; j < op.k; ++j) sub |= ((x >> idx_of(op.a[j])) & 1) << j;
+            E[x * d + x] = o.m[sub];
+        }
+    }
+    return E;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B, size_t d) {
+    std::vector<cd> C(d * d, cd(0, 0));
+    for (size_t i = 0; i < d; ++i)
+        for (size_t k = 0; k < d; ++k) {
+            cd a = A[i * d + k];
+            if (a == cd(0, 0)) continue;
+            for (size_t j = 0; j < d; ++j) C[i * d + j] += a * B[k * d + j];
+        }
+    return C;
+}
+
+std::vector<POp> fuse(const std::vector<POp> &in, int f) {
+    if (f < 2) return in;
+    std::vector<POp> out;
+    size_t i = 0;
+    while (i < in.size()) {
+        if (!in[i].fusable) {
+            out.push_back(in[i++]);
+            continue;
+        }
+        uint32_t mask = in[i].regmask;
+        size_t j = i + 1;
+        while (j < in.size() && in[j].fusable && popc(mask | in[j].regmask) <= f) {
+            mask |= in[j].regmask;
+            ++j;
+        }
+        if (j == i + 1) {
+            out.push_back(in[i++]);
+            continue;
+        }
+        std::vector<int> pos;
+        for (int p = 0; p < 32; ++p)
+            if ((mask >> p) & 1) pos.push_back(p);
+        size_t d = size_t(1) << pos.size();
+        std::vector<cd> M(d * d, cd(0, 0));
+        for (size_t t = 0; t < d; ++t) M[t * d + t] = 1.0;
+        for (size_t t = i; t < j; ++t) M = matmul(embed(in[t], pos), M, d);
+        POp F;
+        std::memset(&F.op, 0, sizeof(F.op));
+        F.op.type = OP_DENSE;
+        F.op.k = (uint8_t)pos.size();
+        for (size_t t = 0; t < pos.size(); ++t) F.op.a[t] = (uint8_t)pos[t];
+        F.op.gate = in[i].op.gate;
+        F.m = std::move(M);
+        F.fusable = true;
+        F.regmask = mask;
+        out.push_back(std::move(F));
+        i = j;
+    }
+    return out;
+}
+
+}  // namespace
+
+static void lower_section(Plan &P, int si) {
+    HostSection &S = P.sections[si];
+    const int C = (int)S.phys_local.size();
+    const int R = std::min(P.r, C);
+    const std::vector<int> &layout = S.layout_at;
+    const int n = P.n;
+
+    // slot of a logical qubit (rank of its physical bit among the chunk's), -1 if non-local
+    std::vector<int> slot(n, -1);
+    for (int q = 0; q < n; ++q) {
+        auto it = std::find(S.phys_local.begin(), S.phys_local.end(), layout[q]);
+        if (it != S.phys_local.end()) slot[q] = (int)(it - S.phys_local.begin());
+    }
+    std::vector<int> slot_q(C);  // slot -> logical qubit
+    for (int q = 0; q < n; ++q)
+        if (slot[q] >= 0) slot_q[slot[q]] = q;
+
+    DevSection ds;
+    std::memset(&ds, 0, sizeof(ds));
+    for (int s = 0; s < C; ++s) ds.slot_phys[s] = (uint8_t)S.phys_local[s];
+    {
+        int t = 0;
+        for (int p = 0; p < n; ++p)
+            if (std::find(S.phys_local.begin(), S.phys_local.end(), p) == S.phys_local.end())
+                ds.nl_phys[t++] = (uint8_t)p;
+        ds.n_nl = (uint32_t)t;
+    }
+    ds.c = (uint32_t)C;
+    ds.phase_begin = (uint32_t)P.dphase.size();
+    ds.param_slot = (uint32_t)P.n_param_ops;
+
+    // position labels: pos2q[pos] = logical qubit held by data position pos
+    std::vector<int> pos2q(C), q2pos(n, -1);
+    auto set_map = [&](const std::vector<int> &regq) {
+        std::vector<int> rest;
+        for (int s = 0; s < C; ++s) {
+            int q = slot_q[s];
+            if (std::find(regq.begin(), regq.end(), q) == regq.end()) rest.push_back(q);
+        }
+        // registers: chosen qubits by slot ascending; threads: remaining qubits by slot ascending
+        std::vector<int> rq = regq;
+        std::sort(rq.begin(), rq.end(), [&](int a, int b) { return slot[a] < slot[b]; });
+        for (int i = 0; i < R; ++i) pos2q[i] = rq[i];
+        for (int i = 0; i < C - R; ++i) pos2q[R + i] = rest[i];
+        std::fill(q2pos.begin(), q2pos.end(), -1);
+        for (int i = 0; i < C; ++i) q2pos[pos2q[i]] = i;
+    };
+    auto src_of = [&](int q) -> uint8_t {
+        if (q2pos[q] >= 0) return (uint8_t)q2pos[q];
+        return (uint8_t)(SRC_GLOBAL + layout[q]);
+    };
+
+    std::vector<int> rem = S.gates;
+    bool first = true;
+    DevPhase cur;
+    std::memset(&cur, 0, sizeof(cur));
+    auto snapshot = [&](uint8_t *dst) {
+        for (int p = 0; p < C; ++p) dst[p] = (uint8_t)slot[pos2q[p]];
+    };
+
+    if (rem.empty()) {
+        // identity section: one phase, registers on the highest slots
+        std::vector<int> regq;
+        for (int s = C - 1; s >= 0 && (int)regq.size() < R; --s) regq.push_back(slot_q[s]);
+        set_map(regq);
+        snapshot(cur.rd);
+        snapshot(cur.wr);
+        cur.op_begin = cur.op_end = (uint32_t)P.dops.size();
+        P.dphase.push_back(cur);
+    }
+    while (!rem.empty()) {
+        // choose the register qubits: in-order greedy with blocking
+        uint64_t chosen = 0, blocked = 0;
+        for (int idx : rem) {
+            const GateRec &g = P.gates[idx];
+            uint64_t rn = need_reg(g);
+            if (g.qmask & blocked) {
+                blocked |= g.qmask;
+                continue;
+            }
+            if (popc(chosen | rn) <= R)
+                chosen |= rn;
+            else
+                blocked |= g.qmask;
+        }
+        std::vector<int> regq;
+        for (int q = 0; q < n; ++q)
+            if ((chosen >> q) & 1) regq.push_back(q);
+        if (!first) {
+            // keep qubits already in registers when there is room (no preference otherwise)
+            for (int p = 0; p < R && (int)regq.size() < R; ++p)
+                if (std::find(regq.begin(), regq.end(), pos2q[p]) == regq.end())
+                    regq.push_back(pos2q[p]);
+        }
+        // fill from the highest slots so the lowest slots stay on threads (coalescing)
+        for (int s = C - 1; s >= 0 && (int)regq.size() < R; --s)
+            if (std::find(regq.begin(), regq.end(), slot_q[s]) == regq.end())
+                regq.push_back(slot_q[s]);
+
+        if (!first) {
+            snapshot(cur.wr);
+            P.dphase.push_back(cur);
+        }
+        set_map(regq);
+        std::memset(&cur, 0, sizeof(cur));
+        snapshot(cur.rd);
+        cur.op_begin = (uint32_t)P.dops.size();
+
+        // scan
+        std::vector<POp> pops;
+        std::vector<int> next;
+        blocked = 0;
+        for (int idx : rem) {
+            const GateRec &g = P.gates[idx];
+            bool ok = !(g.qmask & blocked);
+            if (ok) {
+                uint64_t rn = need_reg(g);
+                for (int q = 0; q < n; ++q)
+                    if (((rn >> q) & 1) && !(q2pos[q] >= 0 && q2pos[q] < R)) ok = false;
+            }
+            if (!ok) {
+                blocked |= g.qmask;
+                next.push_back(idx);
+                continue;
+            }
+            POp o;
+            std::memset(&o.op, 0, sizeof(o.op));
+            o.op.gate = idx;
+            if (g.is_swap) {
+                // relabel: the two positions exchange the qubits they stand for
+                int pa = q2pos[g.q[0]], pb = q2pos[g.q[1]];
+                std::swap(pos2q[pa], pos2q[pb]);
+                q2pos[g.q[0]] = pb;
+                q2pos[g.q[1]] = pa;
+                continue;
+            }
+            if (is_param_rot(g)) {
+                RotKind rk = g.kind == QSV_RX ? ROT_RX : g.kind == QSV_RY ? ROT_RY
+                           : g.kind == QSV_RZ ? ROT_RZ : ROT_P;
+                o.op.rot = rk;
+                o.op.k = 1;
+                o.op.arg = g.param;
+                if (rk == ROT_RX || rk == ROT_RY) {
+                    o.op.type = OP_PROT;
+                    o.op.a[0] = (uint8_t)q2pos[g.q[0]];
+                    P.flops += 16.0 * std::ldexp(1.0, n);
+                } else {
+                    o.op.type = OP_PDIAG;
+                    o.op.a[0] = src_of(g.q[0]);
+                    P.flops += 6.0 * std::ldexp(1.0, n);
+                }
+                ++P.n_param_ops;
+                ++ds.n_params_used;
+                pops.push_back(std::move(o));
+                continue;
+            }
+            if (g.kind == QSV_X) {
+                o.op.type = OP_XREG;
+                o.op.k = 1;
+                o.op.a[0] = (uint8_t)q2pos[g.q[0]];
+                o.fusable = true;
+                o.regmask = 1u << o.op.a[0];
+            } else if (g.kind == QSV_CX) {
+                o.op.type = OP_CX;
+                o.op.k = 2;
+                o.op.a[0] = (uint8_t)q2pos[g.q[1]];
+                o.op.a[1] = src_of(g.q[0]);
+                o.fusable = o.op.a[1] < R;
+                o.regmask = (1u << o.op.a[0]) | (o.fusable ? (1u << o.op.a[1]) : 0u);
+            } else if (g.diagonal) {
+                o.op.type = OP_DIAG;
+                o.op.k = (uint8_t)g.nq;
+                size_t d = size_t(1) << g.nq;
+                o.m.resize(d);
+                for (size_t t = 0; t < d; ++t) o.m[t] = g.m[t * d + t];
+                bool allreg = true;
+                for (int j = 0; j < g.nq; ++j) {
+                    o.op.a[j] = src_of(g.q[j]);
+                    if (o.op.a[j] >= R) allreg = false;
+                    else o.regmask |= 1u << o.op.a[j];
+                }
+                o.fusable = allreg;
+            } else {
+                o.op.type = OP_DENSE;
+                o.op.k = (uint8_t)g.nq;
+                int keys[5];
+                for (int j = 0; j < g.nq; ++j) keys[j] = q2pos[g.q[j]];
+                std::vector<int> order;
+                o.m = sorted_matrix(g.m, g.nq, keys, order);
+                for (int t = 0; t < g.nq; ++t) {
+                    o.op.a[t] = (uint8_t)keys[order[t]];
+                    o.regmask |= 1u << o.op.a[t];
+                }
+                o.fusable = true;
+            }
+            pops.push_back(std::move(o));
+        }
+        int f = std::min(P.opt.fusion_max_qubits, std::min(R, 4));
+        std::vector<POp> fused = fuse(pops, f);
+        for (POp &o : fused) {
+            if (o.op.type == OP_DENSE || o.op.type == OP_DIAG) {
+                o.op.arg = (int32_t)P.dmats.size();
+                P.dmats.insert(P.dmats.end(), o.m.begin(), o.m.end());
+            }
+            if (o.op.type == OP_DENSE) {
+                P.flops += 8.0 * std::ldexp(1.0, o.op.k) * std::ldexp(1.0, n);
+                P.kmax = std::max(P.kmax, (int)o.op.k);
+            }
+            if (o.op.type == OP_DIAG) P.flops += 6.0 * std::ldexp(1.0, n);
+            P.dops.push_back(o.op);
+        }
+        cur.op_end = (uint32_t)P.dops.size();
+        rem.swap(next);
+        first = false;
+    }
+    if (!S.gates.empty()) {
+        snapshot(cur.wr);
+        P.dphase.push_back(cur);
+    }
+    ds.phase_end = (uint32_t)P.dphase.size();
+    P.dsec.push_back(ds);
+}
+
+// ---------------------------------------------------------------------------
+// per-gate op list
+
+static void lower_per_gate(Plan &P) {
+    P.pg.clear();
+    for (size_t i = 0; i < P.gates.size(); ++i) {
+        const GateRec &g = P.gates[i];
+        PgOp o;
+        std::memset(&o, 0, sizeof(o));
+        o.gate = (int32_t)i;
+        o.k = (uint8_t)g.nq;
+        for (int j = 0; j < g.nq; ++j) o.q[j] = (uint8_t)g.q[j];
+        if (g.param >= 0) {
+            o.kind = 0;  // resolved at run time (not supported in per-gate mode)
+        } else if (g.kind == QSV_X) {
+            o.kind = PG_X;
+        } else if (g.kind == QSV_CX) {
+            o.kind = PG_CX;
+        } else if (g.kind == QSV_SWAP) {
+            o.kind = PG_SWAP;
+        } else if (g.kind == QSV_CZ || g.kind == QSV_CP) {
+            o.kind = PG_CPHASE;
+            o.arg = (int32_t)P.dmats.size();
+            P.dmats.push_back(g.m[15]);
+        } else if (g.nq == 1 && g.diagonal && g.m[0] == cd(1.0, 0.0)) {
+            o.kind = PG_PHASE1;
+            o.arg = (int32_t)P.dmats.size();
+            P.dmats.push_back(g.m[3]);
+        } else if (g.nq == 1 && g.diagonal) {
+            o.kind = PG_DIAG1;
+            o.arg = (int32_t)P.dmats.size();
+            P.dmats.push_back(g.m[0]);
+            P.dmats.push_back(g.m[3]);
+        } else {
+            o.kind = PG_DENSE;
+            int keys[5];
+            for (int j = 0; j < g.nq; ++j) keys[j] = g.q[j];
+            std::vector<int> order;
+            std::vector<cd> m = sorted_matrix(g.m, g.nq, keys, order);
+            for (int t = 0; t < g.nq; ++t) o.q[t] = (uint8_t)g.q[order[t]];
+            o.arg = (int32_t)P.dmats.size();
+            P.dmats.insert(P.dmats.end(), m.begin(), m.end());
+        }
+        P.pg.push_back(o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+static std::atomic<uint64_t> g_plan_uid{1};
+
+qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_gate *g,
+                      size_t ng, Plan &P, std::string &err) {
+    if (dt != QSV_C64 && dt != QSV_C128) {
+        err = "dtype must be QSV_C64 or QSV_C128";
+        return QSV_E_INVALID;
+    }
+    if (n < 1 || n > QSV_MAX_QUBITS) {
+        err = "n must be in [1, " + std::to_string(QSV_MAX_QUBITS) + "]";
+        return QSV_E_INVALID;
+    }
+    if (ng > 0 && !g) {
+        err = "gates pointer is NULL";
+        return QSV_E_INVALID;
+    }
+    qsv_options def;
+    default_options(dt, def);
+    qsv_options o = opt_in;
+    if (o.chunk_bits == 0) o.chunk_bits = def.chunk_bits;
+    if (o.pinned_low_bits < 0) o.pinned_low_bits = def.pinned_low_bits;
+    if (o.register_bits == 0) o.register_bits = def.register_bits;
+    if (o.chunk_bits < 1 || o.chunk_bits > 14) {
+        err = "chunk_bits must be in [1, 14] (the chunk lives in on-chip memory)";
+        return QSV_E_INVALID;
+    }
+    if (o.register_bits < 1 || o.register_bits > 5) {
+        err = "register_bits must be in [1, 5]";
+        return QSV_E_INVALID;
+    }
+    if (o.swap_mode != QSV_SWAP_REMAP && o.swap_mode != QSV_SWAP_MATERIALIZE) {
+        err = "swap_mode must be QSV_SWAP_REMAP or QSV_SWAP_MATERIALIZE";
+        return QSV_E_INVALID;
+    }
+    if (o.fusion_max_qubits < 0 || o.fusion_max_qubits > 5) {
+        err = "fusion_max_qubits must be in [0, 5]";
+        return QSV_E_INVALID;
+    }
+    size_t bytes_per_amp = dt == QSV_C64 ? 8 : 16;
+    if ((size_t(1) << std::min(o.chunk_bits, n)) * bytes_per_amp > 128 * 1024) {
+        err = "chunk of 2^chunk_bits amplitudes exceeds 128 KiB of LDS";
+        return QSV_E_INVALID;
+    }
+    P = Plan();
+    P.n = n;
+    P.dtype = dt;
+    if (!validate_and_build(n, g, ng, P.gates, P.n_params, err)) return QSV_E_INVALID;
+    int maxk = 1;
+    for (const GateRec &r : P.gates)
+        if (!r.diagonal && !r.is_swap && r.kind != QSV_CX) maxk = std::max(maxk, r.nq);
+    P.c = std::min(o.chunk_bits, n);
+    // a dense gate must fit in one thread's registers
+    P.r = std::min(std::max(o.register_bits, maxk), P.c);
+    if (maxk > P.c) {
+        err = "a gate acts on more qubits than the chunk holds";
+        return QSV_E_INVALID;
+    }
+    if (P.c - P.r > 10) {
+        err = "chunk_bits - register_bits must be <= 10 (1024 threads per workgroup)";
+        return QSV_E_INVALID;
+    }
+    int maxlocal = 1;
+    for (const GateRec &r : P.gates) maxlocal = std::max(maxlocal, r.nq);
+    if (o.pinned_low_bits > P.c - maxlocal) o.pinned_low_bits = std::max(0, P.c - maxlocal);
+    if (o.pinned_low_bits > n) o.pinned_low_bits = n;
+    o.register_bits = P.r;
+    o.chunk_bits = P.c;
+    P.opt = o;
+
+    block_circuit(P);
+    for (size_t s = 0; s < P.sections.size(); ++s) lower_section(P, (int)s);
+    lower_per_gate(P);
+    P.uid = g_plan_uid.fetch_add(1);
+    return QSV_OK;
+}
+
+}  // namespace qsv

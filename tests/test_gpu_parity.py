@@ -1,0 +1,280 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (written here, from the precision targets of the path): complex128
+1 - F < 1e-12, complex64 1 - F < 1e-5 (normalised fidelity, FP64 sums);
+pure permutation circuits bit-exact.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_02957_amd import binding as B
+from paper_2102_02957_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.QSV_C128: 1e-12, B.QSV_C64: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def ctxs(torch):
+    return {B.QSV_C128: B.Context(B.QSV_C128), B.QSV_C64: B.Context(B.QSV_C64)}
+
+
+def tdtype(torch, dt):
+    return torch.complex128 if dt == B.QSV_C128 else torch.complex64
+
+
+def to_dev(torch, psi, dt):
+    return torch.from_numpy(np.asarray(psi, dtype=np.complex128)).to(tdtype(torch, dt)).cuda().contiguous()
+
+
+def random_state(n, seed):
+    rng = np.random.default_rng(1000 + seed)
+    psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    return psi / np.linalg.norm(psi)
+
+
+def run_gpu(torch, ctxs, n, gates, dt, psi0=None, mode=B.QSV_MODE_BLOCKED, **opts):
+    plan = B.Plan(n, gates, dt, **opts)
+    ctx = ctxs[dt]
+    if psi0 is None:
+        st = torch.empty(1 << n, dtype=tdtype(torch, dt), device="cuda")
+        ctx.init_basis(st, n, 0)
+    else:
+        st = to_dev(torch, psi0, dt)
+    ctx.apply(plan, st, mode)
+    torch.cuda.synchronize()
+    return st.cpu().numpy().astype(np.complex128), plan
+
+
+def assert_close(got, want, dt, what=""):
+    f = oracle.fidelity(got, want)
+    err = 1.0 - f
+    assert err < TOL[dt], "%s: 1-F = %.3e, max|d| = %.3e" % (what, err, oracle.max_abs_diff(got, want))
+    assert abs(oracle.norm2(got) - 1.0) < (1e-12 if dt == B.QSV_C128 else 1e-5)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("mode", [B.QSV_MODE_BLOCKED, B.QSV_MODE_PER_GATE])
+def test_config_plain_12q(torch, ctxs, dt, mode):
+    """12 qubits, 20 layers of U3 on every qubit + CX on a random matching."""
+    n = 12
+    gates = W.u3_cx_layers(n, 20, 0)
+    got, _ = run_gpu(torch, ctxs, n, gates, dt, mode=mode)
+    assert_close(got, oracle.apply_circuit(n, gates), dt, "c1")
+
+
+RANDOM_CASES = [
+    # n, chunk_bits, register_bits, pinned, fusion, seed
+    (1, 0, 0, 0, 0, 0),
+    (2, 0, 0, 0, 2, 1),
+    (3, 2, 1, 0, 0, 2),
+    (5, 3, 2, 0, 2, 3),
+    (7, 4, 2, 1, 2, 4),
+    (9, 6, 3, 2, 3, 5),
+    (10, 8, 4, 3, 4, 6),
+    (13, 12, 4, 3, 2, 7),
+    (14, 9, 4, 2, 0, 8),
+    (16, 12, 4, 3, 2, 9),
+    (17, 11, 5, 4, 3, 10),
+    (18, 13, 5, 4, 4, 11),
+]
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("n,c,r,L,f,seed", RANDOM_CASES)
+def test_random_circuits(torch, ctxs, dt, n, c, r, L, f, seed):
+    gates = W.random_circuit(n, 6 * n + 10, seed, max_unitary_qubits=min(3, n))
+    psi0 = random_state(n, seed)
+    opts = dict(fusion_max_qubits=f)
+    if c:
+        opts.update(chunk_bits=c, register_bits=r, pinned_low_bits=L)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, **opts)
+    assert_close(got, want, dt, "blocked")
+    got2, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, mode=B.QSV_MODE_PER_GATE, **opts)
+    assert_close(got2, want, dt, "per-gate")
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("k", [4, 5])
+def test_wide_unitaries(torch, ctxs, dt, k):
+    n = 12
+    rng = np.random.default_rng(k)
+    gates = []
+    for _ in range(6):
+        qs = tuple(int(v) for v in rng.choice(n, size=k, replace=False))
+        gates.append(W.Gate("unitary", qs, (), W.haar_unitary(rng, 1 << k)))
+    psi0 = random_state(n, k)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=10, register_bits=k)
+    assert_close(got, want, dt)
+    got, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, mode=B.QSV_MODE_PER_GATE)
+    assert_close(got, want, dt)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("mode", [B.QSV_MODE_BLOCKED, B.QSV_MODE_PER_GATE])
+@pytest.mark.parametrize("swap_mode", [B.QSV_SWAP_REMAP, B.QSV_SWAP_MATERIALIZE])
+def test_permutation_circuits_bit_exact(torch, ctxs, dt, mode, swap_mode):
+    """X, CX and SWAP only move amplitudes: the result is bit-identical."""
+    n = 15
+    gates = W.random_circuit(n, 120, 21, kinds=["x", "cx", "swap"])
+    psi0 = random_state(n, 3)
+    if dt == B.QSV_C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, mode=mode, chunk_bits=8,
+                     register_bits=3, pinned_low_bits=2, fusion_max_qubits=0, swap_mode=swap_mode)
+    if dt == B.QSV_C64:
+        want = want.astype(np.complex64)
+        got = got.astype(np.complex64)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_materialised_swaps(torch, ctxs, dt):
+    n = 16
+    gates = W.quantum_volume(n, 8, 5)
+    psi0 = random_state(n, 5)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=9, register_bits=4,
+                        swap_mode=B.QSV_SWAP_MATERIALIZE)
+    assert plan.stats()["n_chunk_swaps"] > 0
+    assert_close(got, want, dt)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_qv_and_u3cx_midsize(torch, ctxs, dt):
+    n = 20
+    for gates in (W.quantum_volume(n, n, 1), W.u3_cx_layers(n, 10, 1)):
+        want = oracle.apply_circuit(n, gates)
+        got, _ = run_gpu(torch, ctxs, n, gates, dt)
+        assert_close(got, want, dt)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_qft_basis_closed_form(torch, ctxs, dt):
+    n = 22
+    x = W.random_basis_index(n, 0)
+    plan = B.Plan(n, W.qft(n), dt)
+    ctx = ctxs[dt]
+    st = torch.empty(1 << n, dtype=tdtype(torch, dt), device="cuda")
+    ctx.init_basis(st, n, x)
+    ctx.apply(plan, st)
+    got = st.cpu().numpy().astype(np.complex128)
+    want = oracle.closed_forms.qft_basis_amplitudes(n, x, range(1 << n)) if n <= 16 else None
+    ys = np.random.default_rng(0).integers(0, 1 << n, 4096)
+    want = oracle.closed_forms.qft_basis_amplitudes(n, x, ys)
+    tol = 1e-13 if dt == B.QSV_C128 else 2e-6
+    assert np.max(np.abs(got[ys] - want)) < tol * 1
+    assert abs(oracle.norm2(got) - 1.0) < (1e-12 if dt == B.QSV_C128 else 1e-5)
+
+
+def test_determinism(torch, ctxs):
+    n = 18
+    gates = W.quantum_volume(n, n, 9)
+    a, _ = run_gpu(torch, ctxs, n, gates, B.QSV_C128)
+    b, _ = run_gpu(torch, ctxs, n, gates, B.QSV_C128)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_reductions(torch, ctxs, dt):
+    n = 17
+    ctx = ctxs[dt]
+    a = random_state(n, 1) * 1.3
+    b = random_state(n, 2)
+    ta, tb = to_dev(torch, a, dt), to_dev(torch, b, dt)
+    a_ = ta.cpu().numpy().astype(np.complex128)
+    b_ = tb.cpu().numpy().astype(np.complex128)
+    nrm = ctx.norm(ta, n).item()
+    assert abs(nrm - oracle.norm2(a_)) < 1e-12 * nrm
+    ov = ctx.overlap(ta, tb, n).cpu().numpy()
+    want = oracle.overlap(a_, b_)
+    assert abs(complex(ov[0], ov[1]) - want) < 1e-12
+    assert abs(ov[2] - oracle.norm2(a_)) < 1e-12 * ov[2] and abs(ov[3] - oracle.norm2(b_)) < 1e-12
+    terms = oracle.ring_zz_terms(n) + [(0.25, 0b101), (-1.5, 1 << (n - 1))]
+    e = ctx.expval(ta, n, terms).item()
+    assert abs(e - oracle.zstring_expval(a_, n, terms)) < 1e-11
+    nn = ctx.normalize(ta, n).item()
+    assert abs(nn - oracle.norm2(a_)) < 1e-12 * nn
+    assert abs(ctx.norm(ta, n).item() - 1.0) < (1e-14 if dt == B.QSV_C128 else 1e-6)
+
+
+def test_sections_prefix(torch, ctxs):
+    """Checkpoint/resume: running sections [0, k) then [k, S) equals one run,
+    and each prefix is a valid state of the reordered circuit prefix."""
+    n = 16
+    gates = W.quantum_volume(n, n, 2)
+    plan = B.Plan(n, gates, B.QSV_C128, chunk_bits=8)
+    S = plan.stats()["n_sections"]
+    ctx = ctxs[B.QSV_C128]
+    st = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    ctx.init_basis(st, n, 0)
+    k = S // 2
+    ctx.apply_sections(plan, st, 0, k)
+    ops = plan.export()
+    cut, seen = 0, 0
+    for i, op in enumerate(ops):
+        if op[0] == "end":
+            seen += 1
+            if seen == k:
+                cut = i + 1
+                break
+    prefix_gates = [gates[op[1]] for op in ops[:cut] if op[0] == "gate"]
+    want = oracle.apply_circuit(n, prefix_gates)
+    assert 1 - oracle.fidelity(st.cpu().numpy(), want) < 1e-12
+    ctx.apply_sections(plan, st, k, S)
+    assert 1 - oracle.fidelity(st.cpu().numpy(), oracle.apply_circuit(n, gates)) < 1e-12
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_params_batch(torch, ctxs, dt):
+    """Parameter-bound RY/RZ gates, several parameter sets in one launch."""
+    n, layers, batch = 10, 3, 4
+    tmpl = W.hardware_efficient_ansatz(n, layers)
+    theta = W.ansatz_parameters(n, layers, batch, 5)
+    plan = B.Plan(n, tmpl, dt, chunk_bits=7, register_bits=3)
+    ctx = ctxs[dt]
+    st = torch.empty(batch << n, dtype=tdtype(torch, dt), device="cuda")
+    for b in range(batch):
+        ctx.init_basis(st[b << n:(b + 1) << n], n, 0)
+    ctx.apply_params(plan, st, torch.from_numpy(theta).cuda())
+    out = st.cpu().numpy().astype(np.complex128).reshape(batch, -1)
+    for b in range(batch):
+        want = oracle.apply_circuit(n, oracle.bind_params(tmpl, theta[b]))
+        assert_close(out[b], want, dt)
+
+
+def test_empty_and_tiny(torch, ctxs):
+    for n in (1, 2, 3):
+        got, _ = run_gpu(torch, ctxs, n, [], B.QSV_C128, psi0=random_state(n, 0))
+        assert np.allclose(got, random_state(n, 0), atol=1e-15)
+    got, _ = run_gpu(torch, ctxs, 1, [W.Gate("h", (0,))], B.QSV_C128)
+    assert np.allclose(got, [2 ** -0.5, 2 ** -0.5], atol=1e-15)
+
+
+def test_invalid_calls(torch, ctxs):
+    ctx = ctxs[B.QSV_C128]
+    plan = B.Plan(10, W.ghz(10), B.QSV_C64)
+    st = torch.zeros(1 << 10, dtype=torch.complex128, device="cuda")
+    with pytest.raises(B.QsvError):
+        ctx.apply(plan, st)  # dtype mismatch
+    with pytest.raises(B.QsvError):
+        ctx.init_basis(st, 10, 1 << 10)
+    p2 = B.Plan(10, W.ghz(10), B.QSV_C128)
+    with pytest.raises(B.QsvError):
+        ctx.apply(p2, st, mode=7)

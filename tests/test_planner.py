@@ -1,0 +1,193 @@
+"""Host planner through the C ABI (CPU only: planning needs no GPU).
+
+The exported blocked plan (chunk_swaps, begin/end of sections, gates on
+physical qubits) is executed by the oracle's plan executor, which checks that
+every in-section gate is chunk-local and that every gate runs once; the
+result must equal the plain circuit (Sec. IV-A: blocking only reorders
+commuting gates and inserts noiseless swaps)."""
+
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_02957_amd import binding as B
+from paper_2102_02957_amd import workloads as W
+
+
+def plan_matches_circuit(n, gates, dt=B.QSV_C128, **kw):
+    p = B.Plan(n, gates, dt, **kw)
+    st = p.stats()
+    ops = p.export()
+    rng = np.random.default_rng(n)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    got = oracle.run_plan(n, gates, ops, st["final_perm"], st["chunk_bits"],
+                          diag_free=bool(st["diag_free"]), psi=psi0)
+    want = oracle.apply_circuit(n, gates, psi0)
+    assert np.max(np.abs(got - want)) < 1e-12
+    return st, ops
+
+
+CASES = [
+    ("u3cx", lambda n, s: W.u3_cx_layers(n, 6, s)),
+    ("qv", lambda n, s: W.quantum_volume(n, n, s)),
+    ("qft", lambda n, s: W.qft(n)),
+    ("random", lambda n, s: W.random_circuit(n, 80, s, max_unitary_qubits=3)),
+    ("ghz", lambda n, s: W.ghz(n)),
+]
+
+
+@pytest.mark.parametrize("name,builder", CASES)
+@pytest.mark.parametrize("n,c", [(6, 3), (9, 4), (11, 6), (12, 12)])
+@pytest.mark.parametrize("mode", [B.QSV_SWAP_REMAP, B.QSV_SWAP_MATERIALIZE])
+def test_plan_equals_circuit(name, builder, n, c, mode):
+    gates = builder(n, 3)
+    st, ops = plan_matches_circuit(n, gates, chunk_bits=c, swap_mode=mode,
+                                   register_bits=min(3, c), pinned_low_bits=min(1, c - 3) if c > 3 else 0)
+    assert st["n_sections"] >= 1
+    if n <= c:
+        assert st["n_sections"] == 1
+    if mode == B.QSV_SWAP_REMAP:
+        assert st["final_perm"] == list(range(n))
+
+
+@pytest.mark.parametrize("diag_free", [0, 1])
+def test_qft_diag_free_fewer_sections(diag_free):
+    n = 14
+    st, _ = plan_matches_circuit(n, W.qft(n), chunk_bits=6, diag_free=diag_free,
+                                 pinned_low_bits=0)
+    if diag_free:
+        assert st["n_sections"] <= 6
+    else:
+        assert st["n_sections"] > 6
+
+
+def test_diagonal_only_circuit_single_section():
+    n = 10
+    gates = [("cp", (a, b), (0.1 * a + 0.01 * b,), None, -1)
+             for a in range(n) for b in range(a + 1, n)]
+    st, _ = plan_matches_circuit(n, gates, chunk_bits=4, diag_free=1, pinned_low_bits=0)
+    assert st["n_sections"] == 1
+
+
+def test_global_only_gates():
+    """Every gate on qubits outside the first chunk."""
+    n = 10
+    gates = [("h", (q,), (), None, -1) for q in range(6, 10)] + [("cx", (9, 7), (), None, -1)]
+    plan_matches_circuit(n, gates, chunk_bits=4, pinned_low_bits=0)
+
+
+def test_c_equals_n_minus_1():
+    n = 9
+    plan_matches_circuit(n, W.quantum_volume(n, n, 1), chunk_bits=n - 1, register_bits=3)
+
+
+def test_pinned_low_bits_always_local():
+    n, c, L = 12, 6, 3
+    p = B.Plan(n, W.quantum_volume(n, n, 4), B.QSV_C128, chunk_bits=c, pinned_low_bits=L,
+               register_bits=3)
+    for op in p.export():
+        if op[0] == "begin":
+            assert op[1] & ((1 << L) - 1) == (1 << L) - 1
+
+
+@pytest.mark.parametrize("f", [0, 2, 3, 4])
+def test_fusion_counts(f):
+    n = 10
+    gates = W.u3_cx_layers(n, 4, 2)
+    p = B.Plan(n, gates, B.QSV_C128, chunk_bits=n, fusion_max_qubits=f, register_bits=4)
+    st = p.stats()
+    if f >= 2:
+        assert st["n_device_ops"] < len(gates)
+    assert st["n_sections"] == 1
+
+
+def test_deterministic():
+    n = 20
+    g = W.quantum_volume(n, n, 7)
+    a = B.Plan(n, g, B.QSV_C128).export()
+    b = B.Plan(n, g, B.QSV_C128).export()
+    assert a == b
+
+
+def test_progress_every_section_nonempty():
+    n = 16
+    for gates in (W.qft(n), W.quantum_volume(n, n, 3), W.u3_cx_layers(n, 5, 3)):
+        ops = B.Plan(n, gates, B.QSV_C128, chunk_bits=5, register_bits=3, pinned_low_bits=1).export()
+        count = 0
+        for op in ops:
+            if op[0] == "begin":
+                count = 0
+            elif op[0] == "gate":
+                count += 1
+            elif op[0] == "end":
+                assert count > 0
+
+
+def test_section_counts_benchmark_circuits():
+    """Blocking at the benchmark sizes: far fewer HBM passes than gates."""
+    qv = B.Plan(33, W.quantum_volume(33, 33, 0), B.QSV_C128).stats()
+    assert qv["n_gates"] == 528 and qv["n_sections"] < 100
+    qft = B.Plan(26, W.qft(26), B.QSV_C128).stats()
+    assert qft["n_sections"] <= 8
+
+
+@pytest.mark.parametrize("bad,msg", [
+    ([("h", (5,), (), None, -1)], "out of range"),
+    ([("cx", (1, 1), (), None, -1)], "repeated"),
+    ([("unitary", (0, 1), (), None, -1)], "without matrix"),
+    ([("ry", (0,), (0.0,), None, -2)], None),
+    ([("h", (0,), (), None, 3)], "bound parameter"),
+])
+def test_invalid_gates_rejected(bad, msg):
+    if msg is None:
+        B.Plan(4, bad, B.QSV_C128)  # param -2 means unbound: accepted
+        return
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(4, bad, B.QSV_C128)
+    assert e.value.status == -1 and msg in str(e.value)
+
+
+def test_invalid_options_rejected():
+    with pytest.raises(B.QsvError):
+        B.Plan(20, W.ghz(20), B.QSV_C128, chunk_bits=15)
+    with pytest.raises(B.QsvError):
+        B.Plan(20, W.ghz(20), B.QSV_C128, swap_mode=7)
+    with pytest.raises(B.QsvError):
+        B.Plan(35, [], B.QSV_C128)
+    with pytest.raises(B.QsvError):
+        B.Plan(20, W.ghz(20), 3)
+
+
+def test_empty_circuit():
+    st, ops = plan_matches_circuit(5, [], chunk_bits=3)
+    assert st["n_sections"] == 1
+
+
+def test_header_symbols_exported():
+    """Every function declared in include/qsv.h is exported by libqsv.so."""
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    hdr = open(os.path.join(root, "include", "qsv.h")).read()
+    declared = set(re.findall(r"\b(qsv_[a-z_]+)\s*\(", hdr))
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    missing = declared - exported
+    assert not missing, missing
+    assert set(B.EXPORTED) <= exported
+    L = B.lib()
+    for name in declared:
+        getattr(L, name)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(B.QsvError) as e:
+        B.Context(B.QSV_C128)
+    assert e.value.status in (-3, -1)
