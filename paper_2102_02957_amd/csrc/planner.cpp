@@ -113,9 +113,67 @@ int scan_count(const Blocker &B, const std::vector<int> &rem, uint64_t local) {
     return cnt;
 }
 
+// Greedy on the section's actual gate count: starting from the first remaining
+// gate's qubits, repeatedly add the need-set of a remaining gate that raises
+// the number of admitted gates the most (per added qubit if `per_qubit`).
+uint64_t choose_gain(const Blocker &B, const std::vector<int> &rem, uint64_t start, int cap,
+                     bool per_qubit, size_t window) {
+    uint64_t chosen = start | need_local(B.G[rem[0]], B.diag_free);
+    int cur = scan_count(B, rem, chosen);
+    std::vector<uint64_t> seen;
+    while (popc(chosen) < cap) {
+        uint64_t best_add = 0;
+        double best_score = 0.0;
+        seen.clear();
+        const size_t lim = std::min(window, rem.size());
+        for (size_t t = 0; t < lim; ++t) {
+            uint64_t nm = need_local(B.G[rem[t]], B.diag_free) & ~chosen;
+            if (!nm || popc(chosen | nm) > cap) continue;
+            if (std::find(seen.begin(), seen.end(), nm) != seen.end()) continue;
+            seen.push_back(nm);
+            int cnt = scan_count(B, rem, chosen | nm);
+            double score = per_qubit ? double(cnt - cur) / popc(nm) : double(cnt - cur);
+            if (score > best_score) {
+                best_score = score;
+                best_add = nm;
+            }
+        }
+        if (!best_add) break;
+        chosen |= best_add;
+        cur = scan_count(B, rem, chosen);
+    }
+    return chosen;
+}
+
 uint64_t fill_low(uint64_t chosen, int cap, int n) {
     for (int q = 0; q < n && popc(chosen) < cap; ++q) chosen |= bit(q);
     return chosen;
+}
+
+// the candidate chunk sets for one section (remap semantics: logical == physical)
+void chunk_candidates(const Blocker &B, const std::vector<int> &rem, uint64_t start, int c,
+                      int n, std::vector<uint64_t> &out) {
+    out.clear();
+    out.push_back(choose_inorder(B, rem, start, c, 1));
+    uint64_t multi = choose_inorder(B, rem, start, c, 2);
+    out.push_back(multi);
+    // paper order: multi-qubit gates choose first, then 1-qubit gates fill
+    out.push_back(choose_inorder(B, rem, multi, c, 1));
+    out.push_back(choose_gain(B, rem, start, c, false, 96));
+    out.push_back(choose_gain(B, rem, start, c, true, 96));
+    (void)n;
+}
+
+std::vector<int> scan_rest(const Blocker &B, const std::vector<int> &rem, uint64_t local) {
+    std::vector<int> next;
+    uint64_t blocked = 0;
+    for (int idx : rem) {
+        const GateRec &g = B.G[idx];
+        if (!(g.qmask & blocked) && !(need_local(g, B.diag_free) & ~local)) continue;
+        blocked |= g.qmask;
+        next.push_back(idx);
+    }
+    return next;
 }
 
 }  // namespace
@@ -253,16 +311,10 @@ static void block_circuit(Plan &P) {
         // each candidate admits it
         uint64_t start = 0;
         if (!materialise) start = pinned;  // remap: logical == physical, low bits pinned
-        uint64_t cands[3];
-        cands[0] = choose_inorder(B, rem, start, c, 1);
-        cands[1] = choose_inorder(B, rem, start, c, 2);
-        {
-            // paper order: multi-qubit gates choose first, then 1-qubit gates fill
-            uint64_t s = cands[1];
-            cands[2] = choose_inorder(B, rem, s, c, 1);
-        }
+        std::vector<uint64_t> cands, cands2;
+        chunk_candidates(B, rem, start, c, n, cands);
         uint64_t best = 0;
-        int best_cnt = -1;
+        int best_score = -1, best_cnt = -1;
         for (uint64_t cand : cands) {
             uint64_t full = cand;
             if (materialise) {
@@ -271,7 +323,18 @@ static void block_circuit(Plan &P) {
             }
             full = fill_low(full, c, n);
             int cnt = scan_count(B, rem, full);
-            if (cnt > best_cnt) {
+            // one section of lookahead: gates this section plus the best next one
+            int score = cnt;
+            std::vector<int> nxt = scan_rest(B, rem, full);
+            if (!nxt.empty()) {
+                chunk_candidates(B, nxt, start, c, n, cands2);
+                int b2 = 0;
+                for (uint64_t c2 : cands2)
+                    b2 = std::max(b2, scan_count(B, nxt, fill_low(c2, c, n)));
+                score += b2;
+            }
+            if (score > best_score || (score == best_score && cnt > best_cnt)) {
+                best_score = score;
                 best_cnt = cnt;
                 best = full;
             }

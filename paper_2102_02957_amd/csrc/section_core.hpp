@@ -1,0 +1,433 @@
+// Device building blocks of the section kernel, shared by the blocked apply,
+// the batched-trajectory kernel and the adjoint sweep.
+//
+// One workgroup owns one chunk of 2^c amplitudes (Sec. III-B: a chunk is the
+// set of amplitudes sharing the values of the n - c non-local bits; here the
+// non-local bits are arbitrary, so the chunk is gathered from HBM instead of
+// being a contiguous block).  Each of the 2^(c-r) threads holds 2^r amplitudes
+// in registers.  The section's gates run in "phases": during a phase r chunk
+// qubits are register qubits (a gate on them touches only the thread's own
+// registers: the pair-wise update of Sec. II-A, Fig. "u3_gate", done in
+// registers) and the other c - r are spread over the threads.  Between phases
+// the chunk is transposed through LDS.  HBM sees one read at the first phase
+// and one write at the last.
+//
+// Data position p of an amplitude: bits 0..r-1 = register index, bits
+// r..c-1 = thread index.  A phase maps positions to chunk slots (rd at its
+// start, wr at its end; SWAP gates relabel positions mid-phase); a slot maps
+// to a physical bit of the amplitude index.
+#pragma once
+
+#include <type_traits>
+#include <utility>
+
+#include "device.hpp"
+
+namespace qsv {
+namespace sec {
+
+
+template <typename V> __device__ __forceinline__ V cmul(V m, V x) {
+    V r;
+    r.x = m.x * x.x - m.y * x.y;
+    r.y = m.x * x.y + m.y * x.x;
+    return r;
+}
+// Plan tables are read through the constant address space: every workgroup
+// reads the same entries, so the loads become scalar (SGPR) loads even inside
+// loops that contain barriers.
+template <typename X> using cptr = const X __attribute__((address_space(4))) *;
+
+template <typename V> __device__ __forceinline__ V ldc(cptr<V> p) {
+    V r;
+    r.x = p->x;
+    r.y = p->y;
+    return r;
+}
+
+// component-wise select (a select of whole structs becomes a select of their
+// addresses, which would keep the register array in scratch memory)
+template <typename V> __device__ __forceinline__ V sel(bool c, V a, V b) {
+    V r;
+    r.x = c ? a.x : b.x;
+    r.y = c ? a.y : b.y;
+    return r;
+}
+template <typename V> __device__ __forceinline__ V cfma(V m, V x, V acc) {
+    acc.x = fma(m.x, x.x, acc.x);
+    acc.x = fma(-m.y, x.y, acc.x);
+    acc.y = fma(m.x, x.y, acc.y);
+    acc.y = fma(m.y, x.x, acc.y);
+    return acc;
+}
+
+// compile-time loops and index helpers ---------------------------------------
+// Every register index below is a constant expression, so the per-thread
+// amplitude array stays in VGPRs (a runtime index would move it to scratch).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// scatter the bits of g into the R - K register bits not among P (ascending)
+template <int R, int... P> __host__ __device__ constexpr int dep_rest(int g) {
+    constexpr int pos[] = {P...};
+    int out = 0, t = 0;
+    for (int b = 0; b < R; ++b) {
+        bool in = false;
+        for (int j = 0; j < (int)sizeof...(P); ++j) in = in || (pos[j] == b);
+        if (!in) {
+            out |= ((g >> t) & 1) << b;
+            ++t;
+        }
+    }
+    return out;
+}
+// scatter the bits of l into the positions P (bit j of l -> bit P_j)
+template <int... P> __host__ __device__ constexpr int dep_pos(int l) {
+    constexpr int pos[] = {P...};
+    int out = 0;
+    for (int j = 0; j < (int)sizeof...(P); ++j) out |= ((l >> j) & 1) << pos[j];
+    return out;
+}
+
+// dense 2^K x 2^K matrix (row-major, uniform memory) on register positions P...
+template <typename V, int R, int... P>
+__device__ __forceinline__ void dense_apply(V (&a)[1 << R], cptr<V> m) {
+    constexpr int K = sizeof...(P);
+    constexpr int D = 1 << K;
+    static_for<(1 << (R - K))>([&](auto G) __attribute__((always_inline)) {
+        constexpr int b = dep_rest<R, P...>(G.value);
+        V in[D];
+        static_for<D>([&](auto L) __attribute__((always_inline)) { in[L.value] = a[b | dep_pos<P...>(L.value)]; });
+        static_for<D>([&](auto ROW) __attribute__((always_inline)) {
+            V acc;
+            acc.x = 0;
+            acc.y = 0;
+            static_for<D>([&](auto L) __attribute__((always_inline)) { acc = cfma(ldc(m + (ROW.value * D + L.value)), in[L.value], acc); });
+            a[b | dep_pos<P...>(ROW.value)] = acc;
+        });
+    });
+}
+
+// dispatch of runtime positions (ascending) to the compile-time instances
+template <typename V, int R, int P0 = 0>
+__device__ __forceinline__ void dispatch1(V (&a)[1 << R], int a0, cptr<V> m) {
+    if constexpr (P0 < R) {
+        if (a0 == P0) dense_apply<V, R, P0>(a, m);
+        else dispatch1<V, R, P0 + 1>(a, a0, m);
+    }
+}
+template <typename V, int R, int P0 = 0, int P1 = 1>
+__device__ __forceinline__ void dispatch2(V (&a)[1 << R], int a0, int a1, cptr<V> m) {
+    if constexpr (P0 < R - 1) {
+        if constexpr (P1 < R) {
+            if (a0 == P0 && a1 == P1) dense_apply<V, R, P0, P1>(a, m);
+            else dispatch2<V, R, P0, P1 + 1>(a, a0, a1, m);
+        } else {
+            dispatch2<V, R, P0 + 1, P0 + 2>(a, a0, a1, m);
+        }
+    }
+}
+template <typename V, int R, int P0 = 0, int P1 = 1, int P2 = 2>
+__device__ __forceinline__ void dispatch3(V (&a)[1 << R], int a0, int a1, int a2, cptr<V> m) {
+    if constexpr (R >= 3 && P0 < R - 2) {
+        if constexpr (P1 < R - 1) {
+            if constexpr (P2 < R) {
+                if (a0 == P0 && a1 == P1 && a2 == P2) dense_apply<V, R, P0, P1, P2>(a, m);
+                else dispatch3<V, R, P0, P1, P2 + 1>(a, a0, a1, a2, m);
+            } else {
+                dispatch3<V, R, P0, P1 + 1, P1 + 2>(a, a0, a1, a2, m);
+            }
+        } else {
+            dispatch3<V, R, P0 + 1, P0 + 2, P0 + 3>(a, a0, a1, a2, m);
+        }
+    }
+}
+template <typename V, int R, int P0 = 0, int P1 = 1, int P2 = 2, int P3 = 3>
+__device__ __forceinline__ void dispatch4(V (&a)[1 << R], int a0, int a1, int a2, int a3,
+                                          cptr<V> m) {
+    if constexpr (R >= 4 && P0 < R - 3) {
+        if constexpr (P1 < R - 2) {
+            if constexpr (P2 < R - 1) {
+                if constexpr (P3 < R) {
+                    if (a0 == P0 && a1 == P1 && a2 == P2 && a3 == P3)
+                        dense_apply<V, R, P0, P1, P2, P3>(a, m);
+                    else
+                        dispatch4<V, R, P0, P1, P2, P3 + 1>(a, a0, a1, a2, a3, m);
+                } else {
+                    dispatch4<V, R, P0, P1, P2 + 1, P2 + 2>(a, a0, a1, a2, a3, m);
+                }
+            } else {
+                dispatch4<V, R, P0, P1 + 1, P1 + 2, P1 + 3>(a, a0, a1, a2, a3, m);
+            }
+        } else {
+            dispatch4<V, R, P0 + 1, P0 + 2, P0 + 3, P0 + 4>(a, a0, a1, a2, a3, m);
+        }
+    }
+}
+// 1-qubit matrix given by value (parameterised rotations)
+template <typename V, int R, int P>
+__device__ __forceinline__ void apply1_val(V (&a)[1 << R], V m00, V m01, V m10, V m11) {
+    static_for<(1 << (R - 1))>([&](auto G) __attribute__((always_inline)) {
+        constexpr int i0 = dep_rest<R, P>(G.value), i1 = i0 | (1 << P);
+        V x0 = a[i0], x1 = a[i1];
+        V y0 = cmul(m00, x0), y1 = cmul(m10, x0);
+        a[i0] = cfma(m01, x1, y0);
+        a[i1] = cfma(m11, x1, y1);
+    });
+}
+template <typename V, int R, int P = 0>
+__device__ __forceinline__ void dispatch1_val(V (&a)[1 << R], int a0, V m00, V m01, V m10,
+                                              V m11) {
+    if constexpr (P < R) {
+        if (a0 == P) apply1_val<V, R, P>(a, m00, m01, m10, m11);
+        else dispatch1_val<V, R, P + 1>(a, a0, m00, m01, m10, m11);
+    }
+}
+
+// X on register position T, optionally controlled by a bit source
+template <typename V, int R, int T>
+__device__ __forceinline__ void cx_apply(V (&a)[1 << R], bool has_ctl, unsigned src,
+                                         uint32_t pbase, unsigned gbit) {
+    static_for<(1 << (R - 1))>([&](auto G) __attribute__((always_inline)) {
+        constexpr int i0 = dep_rest<R, T>(G.value), i1 = i0 | (1 << T);
+        bool c = true;
+        if (has_ctl) c = src >= SRC_GLOBAL ? (gbit != 0) : (((pbase | i0) >> src) & 1u) != 0;
+        V x0 = a[i0], x1 = a[i1];
+        a[i0] = sel(c, x1, x0);
+        a[i1] = sel(c, x0, x1);
+    });
+}
+template <typename V, int R, int T = 0>
+__device__ __forceinline__ void dispatch_cx(V (&a)[1 << R], int t, bool has_ctl, unsigned src,
+                                            uint32_t pbase, unsigned gbit) {
+    if constexpr (T < R) {
+        if (t == T) cx_apply<V, R, T>(a, has_ctl, src, pbase, gbit);
+        else dispatch_cx<V, R, T + 1>(a, t, has_ctl, src, pbase, gbit);
+    }
+}
+
+__device__ __forceinline__ unsigned src_bit(unsigned s, uint32_t pidx, uint64_t base) {
+    return s >= SRC_GLOBAL ? (unsigned)((base >> (s - SRC_GLOBAL)) & 1ull) : ((pidx >> s) & 1u);
+}
+
+template <typename V> __device__ __forceinline__ int lds_swizzle(int j) {
+    // XOR-fold the higher index bits into the bank-selecting low bits (128 B rows)
+    if constexpr (sizeof(V) == 16) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7);
+    else return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15);
+}
+
+
+// ---- chunk-level steps --------------------------------------------------------
+
+// physical-bit offset of data positions [0, R) -> per-register offsets, plus the
+// thread's own offset from positions [R, R + TB)
+template <typename V, int R>
+__device__ __forceinline__ void chunk_gather(V (&a)[1 << R], const V *__restrict__ st,
+                                             cptr<DevSection> S, cptr<uint8_t> map,
+                                             uint64_t base, unsigned tid, int TB) {
+    uint64_t toff = 0;
+    for (int b = 0; b < TB; ++b) toff |= (uint64_t)((tid >> b) & 1u) << S->slot_phys[map[R + b]];
+    uint64_t rbit[R];
+    static_for<R>([&](auto B) __attribute__((always_inline)) {
+        rbit[B.value] = 1ull << S->slot_phys[map[B.value]];
+    });
+    static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+        uint64_t off = toff;
+        static_for<R>([&](auto B) __attribute__((always_inline)) {
+            if constexpr (((I.value >> B.value) & 1) != 0) off |= rbit[B.value];
+        });
+        a[I.value] = st[base | off];
+    });
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void chunk_scatter(const V (&a)[1 << R], V *__restrict__ st,
+                                              cptr<DevSection> S, cptr<uint8_t> map,
+                                              uint64_t base, unsigned tid, int TB) {
+    uint64_t toff = 0;
+    for (int b = 0; b < TB; ++b) toff |= (uint64_t)((tid >> b) & 1u) << S->slot_phys[map[R + b]];
+    uint64_t rbit[R];
+    static_for<R>([&](auto B) __attribute__((always_inline)) {
+        rbit[B.value] = 1ull << S->slot_phys[map[B.value]];
+    });
+    static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+        uint64_t off = toff;
+        static_for<R>([&](auto B) __attribute__((always_inline)) {
+            if constexpr (((I.value >> B.value) & 1) != 0) off |= rbit[B.value];
+        });
+        st[base | off] = a[I.value];
+    });
+}
+
+// LDS transposition from position->slot map `from` to map `to`.  Threads with
+// active == false take part in the barriers only.
+template <typename V, int R>
+__device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uint8_t> from,
+                                                cptr<uint8_t> to, unsigned tid, int TB,
+                                                bool active) {
+    uint32_t tw = 0, tr = 0;
+    for (int b = 0; b < TB; ++b) {
+        tw |= ((tid >> b) & 1u) << from[R + b];
+        tr |= ((tid >> b) & 1u) << to[R + b];
+    }
+    uint32_t bw[R], br[R];
+    static_for<R>([&](auto B) __attribute__((always_inline)) {
+        bw[B.value] = 1u << from[B.value];
+        br[B.value] = 1u << to[B.value];
+    });
+    __syncthreads();
+    if (active) {
+        static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+            uint32_t j = tw;
+            static_for<R>([&](auto B) __attribute__((always_inline)) {
+                if constexpr (((I.value >> B.value) & 1) != 0) j |= bw[B.value];
+            });
+            lds[lds_swizzle<V>((int)j)] = a[I.value];
+        });
+    }
+    __syncthreads();
+    if (active) {
+        static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+            uint32_t j = tr;
+            static_for<R>([&](auto B) __attribute__((always_inline)) {
+                if constexpr (((I.value >> B.value) & 1) != 0) j |= br[B.value];
+            });
+            a[I.value] = lds[lds_swizzle<V>((int)j)];
+        });
+    }
+}
+
+// Forward application of the ops [o_begin, o_end) of one phase to the
+// registers.  pbase = thread index << R; base = the chunk's physical base index.
+template <typename T, int R, int KMAX>
+__device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<DevOp> ops,
+                                          uint32_t o_begin, uint32_t o_end,
+                                          cptr<typename Amp<T>::V> mats,
+                                          const double *__restrict__ prm, uint32_t pbase,
+                                          uint64_t base) {
+    using V = typename Amp<T>::V;
+    constexpr int RA = 1 << R;
+    for (uint32_t o = o_begin; o < o_end; ++o) {
+        const cptr<DevOp> op = ops + o;
+        const uint32_t type = op->type;
+        const uint32_t k = op->k;
+        if (type == OP_DENSE) {
+            const cptr<V> mm = mats + op->arg;
+            if (k == 1) dispatch1<V, R>(a, op->a[0], mm);
+            else if (k == 2) dispatch2<V, R>(a, op->a[0], op->a[1], mm);
+            else if constexpr (KMAX >= 3) {
+                if (k == 3) dispatch3<V, R>(a, op->a[0], op->a[1], op->a[2], mm);
+                else if constexpr (KMAX >= 4) {
+                    if (k == 4) dispatch4<V, R>(a, op->a[0], op->a[1], op->a[2], op->a[3], mm);
+                    else if constexpr (KMAX >= 5) {
+                        if (op->a[0] == 0 && op->a[4] == 4) dense_apply<V, R, 0, 1, 2, 3, 4>(a, mm);
+                    }
+                }
+            }
+        } else if (type == OP_XREG) {
+            dispatch_cx<V, R>(a, op->a[0], false, 0, pbase, 0);
+        } else if (type == OP_CX) {
+            const unsigned s = op->a[1];
+            const unsigned gbit =
+                s >= SRC_GLOBAL ? (unsigned)((base >> (s - SRC_GLOBAL)) & 1ull) : 0u;
+            dispatch_cx<V, R>(a, op->a[0], true, s, pbase, gbit);
+        } else if (type == OP_DIAG) {
+            const cptr<V> tab = mats + op->arg;
+            if (k == 1) {
+                const V d0 = ldc(tab), d1 = ldc(tab + 1);
+                const unsigned s0 = op->a[0];
+                static_for<RA>([&](auto I) __attribute__((always_inline)) {
+                    const unsigned b0 = src_bit(s0, pbase | I.value, base);
+                    a[I.value] = cmul(sel(b0 != 0, d1, d0), a[I.value]);
+                });
+            } else if (k == 2) {
+                const V d0 = ldc(tab), d1 = ldc(tab + 1), d2 = ldc(tab + 2), d3 = ldc(tab + 3);
+                const unsigned s0 = op->a[0], s1 = op->a[1];
+                static_for<RA>([&](auto I) __attribute__((always_inline)) {
+                    const unsigned b0 = src_bit(s0, pbase | I.value, base);
+                    const unsigned b1 = src_bit(s1, pbase | I.value, base);
+                    const V lo = sel(b0 != 0, d1, d0), hi = sel(b0 != 0, d3, d2);
+                    a[I.value] = cmul(sel(b1 != 0, hi, lo), a[I.value]);
+                });
+            } else {
+                static_for<RA>([&](auto I) __attribute__((always_inline)) {
+                    unsigned idx = 0;
+                    for (uint32_t j = 0; j < k; ++j)
+                        idx |= src_bit(op->a[j], pbase | I.value, base) << j;
+                    a[I.value] = cmul(ldc(tab + idx), a[I.value]);
+                });
+            }
+        } else if (type == OP_PROT) {
+            double sn, cs;
+            sincos(0.5 * prm[op->arg], &sn, &cs);
+            V c0, s0, ms;
+            c0.x = (T)cs;
+            c0.y = 0;
+            if (op->rot == ROT_RY) {
+                s0.x = (T)sn;
+                s0.y = 0;
+                ms.x = (T)-sn;
+                ms.y = 0;
+                dispatch1_val<V, R>(a, op->a[0], c0, ms, s0, c0);
+            } else {  // RX: [[c, -i s], [-i s, c]]
+                ms.x = 0;
+                ms.y = (T)-sn;
+                dispatch1_val<V, R>(a, op->a[0], c0, ms, ms, c0);
+            }
+        } else if (type == OP_PDIAG) {
+            const double th = prm[op->arg];
+            double sn, cs;
+            V d0, d1;
+            if (op->rot == ROT_RZ) {
+                sincos(0.5 * th, &sn, &cs);
+                d0.x = (T)cs;
+                d0.y = (T)-sn;
+                d1.x = (T)cs;
+                d1.y = (T)sn;
+            } else {
+                sincos(th, &sn, &cs);
+                d0.x = 1;
+                d0.y = 0;
+                d1.x = (T)cs;
+                d1.y = (T)sn;
+            }
+            const unsigned s0 = op->a[0];
+            static_for<RA>([&](auto I) __attribute__((always_inline)) {
+                a[I.value] = cmul(sel(src_bit(s0, pbase | I.value, base) != 0, d1, d0), a[I.value]);
+            });
+        }
+    }
+}
+
+// One chunk of one section, forward: gather, phases, scatter.
+template <typename T, int R, int KMAX>
+__device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
+                                          cptr<DevSection> S, cptr<DevPhase> phases,
+                                          cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
+                                          const double *__restrict__ prm, uint64_t chunk,
+                                          typename Amp<T>::V *lds, bool active) {
+    using V = typename Amp<T>::V;
+    const int TB = (int)S->c - R;
+    const unsigned tid = threadIdx.x;
+    uint64_t base = 0;
+    for (uint32_t k = 0; k < S->n_nl; ++k) base |= ((chunk >> k) & 1ull) << S->nl_phys[k];
+    const cptr<DevPhase> ph = phases + S->phase_begin;
+    const int nph = (int)(S->phase_end - S->phase_begin);
+    const uint32_t pbase = tid << R;
+    V a[1 << R];
+    if (active) chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
+    for (int p = 0; p < nph; ++p) {
+        const cptr<DevPhase> P = ph + p;
+        chunk_ops<T, R, KMAX>(a, ops, P->op_begin, P->op_end, mats, prm, pbase, base);
+        if (p + 1 < nph) chunk_transpose<V, R>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
+    }
+    if (active) chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
+}
+
+}  // namespace sec
+}  // namespace qsv
