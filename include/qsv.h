@@ -200,10 +200,14 @@ qsv_status qsv_copy(qsv_ctx *ctx, void *dst, const void *src, int n, void *strea
 /* ---- adjoint gradient -------------------------------------------------- */
 
 /* E_b = <psi_b|H|psi_b>, grad_b[p] = dE_b / dtheta_p for psi_b = U(theta_b)|0>, H = sum of
- * Z-strings, batch states.  psi_dev and lambda_dev are caller workspaces of batch * 2^n
- * amplitudes each (psi_dev holds the final states on return).  energy_dev[batch],
- * grad_dev[batch * P] (device, double; P = stats.n_params).  The reverse sweep follows
- * the blocked plan backwards, one kernel per section holding both chunks. */
+ * Z-strings (terms: host array), for `batch` parameter vectors params_dev[b * P + p]
+ * (device, double; P = stats.n_params).  psi_dev and lambda_dev are caller workspaces of
+ * batch * 2^n amplitudes each; their contents on return are unspecified (the reverse sweep
+ * runs psi back towards |0>).  energy_dev[batch], grad_dev[batch * P] (device, double).
+ * The forward pass is the blocked apply; the reverse sweep follows the blocked plan
+ * backwards, one kernel per section holding the psi and lambda chunks, with per-chunk
+ * FP64 partials reduced in a fixed order.  Needs a remap-mode plan with fusion of at most
+ * 2 qubits (QSV_E_UNSUPPORTED otherwise). */
 qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm *terms,
                             size_t n_terms, const double *params_dev, int batch,
                             void *psi_dev, void *lambda_dev, double *energy_dev,

@@ -335,3 +335,70 @@ class Context:
         _check(lib().qsv_timing_read(self._h, int(which), ctypes.byref(ms), ctypes.byref(cnt),
                                      1 if reset else 0))
         return ms.value, cnt.value
+
+
+def _batch_run(self, plans, offsets, states, norms=None, stream=None):
+    """qsv_batch_run: plans[b] applied to the state at states[offsets[b]:], all
+    initialised to |0>, FP64-renormalised; returns the pre-normalisation norms."""
+    torch = _torch()
+    count = len(plans)
+    if not states.is_cuda or not states.is_contiguous():
+        raise ValueError("states must be a contiguous device tensor")
+    for p, o in zip(plans, offsets):
+        if o + (1 << p.n) > states.numel():
+            raise ValueError("state of a plan runs past the buffer")
+    arr = (ctypes.c_void_p * count)(*[p.handle.value for p in plans])
+    offs = (ctypes.c_uint64 * count)(*[int(o) for o in offsets])
+    norms = torch.empty(count, dtype=torch.float64, device=states.device) if norms is None else norms
+    _check(lib().qsv_batch_run(self._h, count, arr, offs, _ptr(states), _ptr(norms), _stream(stream)))
+    return norms
+
+
+def _adjoint_grad(self, plan, terms, params, psi, lam, energy=None, grad=None, stream=None):
+    """qsv_adjoint_grad: energies [B] and gradients [B, P] of <psi|H|psi>."""
+    torch = _torch()
+    batch = params.shape[0]
+    _check_state(psi, plan.n, batch)
+    _check_state(lam, plan.n, batch)
+    if params.dtype != torch.float64 or not params.is_cuda or not params.is_contiguous():
+        raise ValueError("params must be a contiguous float64 device tensor")
+    arr = (ZTerm * len(terms))()
+    for i, (c, m) in enumerate(terms):
+        arr[i].coeff = float(c)
+        arr[i].zmask = int(m)
+    nparams = plan.stats()["n_params"]
+    energy = torch.empty(batch, dtype=torch.float64, device=psi.device) if energy is None else energy
+    grad = torch.empty(batch, max(1, nparams), dtype=torch.float64, device=psi.device) if grad is None else grad
+    _check(lib().qsv_adjoint_grad(self._h, plan.handle, arr, len(terms), _ptr(params), int(batch),
+                                  _ptr(psi), _ptr(lam), _ptr(energy), _ptr(grad), _stream(stream)))
+    return energy, grad[:, :nparams]
+
+
+Context.batch_run = _batch_run
+Context.adjoint_grad = _adjoint_grad
+
+
+def adjoint_energy_function():
+    """A torch.autograd.Function whose forward returns E_b for params [B, P]
+    (one qsv_adjoint_grad call computes E and dE/dtheta) and whose backward
+    returns gE[:, None] * dE/dtheta."""
+    torch = _torch()
+
+    class AdjointEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, params, qctx, plan, terms):
+            p = params.detach().contiguous()
+            batch = p.shape[0]
+            dt = torch.complex128 if plan.dtype == QSV_C128 else torch.complex64
+            psi = torch.empty(batch << plan.n, dtype=dt, device=p.device)
+            lam = torch.empty_like(psi)
+            e, g = qctx.adjoint_grad(plan, terms, p, psi, lam)
+            fctx.save_for_backward(g)
+            return e
+
+        @staticmethod
+        def backward(fctx, ge):
+            (g,) = fctx.saved_tensors
+            return ge[:, None] * g, None, None, None
+
+    return AdjointEnergy

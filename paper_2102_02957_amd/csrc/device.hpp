@@ -23,16 +23,22 @@ struct DevPlanView {           // device pointers of one uploaded plan
     const DevOp *ops;
     const void *mats;          // V[] in the context's dtype
     const PgOp *pg;
+    const PSlot *pslots;
+    const int32_t *poff, *plist;   // parameter -> param ops (CSR)
 };
 
 // ---- launchers (kernels.hip) ----------------------------------------------
 
 // One section of a blocked plan over `batch` states (state b at state + b * 2^n).
 // lds_bytes == 0 when the section has a single phase.
-// kmax: widest dense op in the plan (selects the kernel instance).
+// kmax: widest dense op in the plan (selects the kernel instance); ptab: the
+// per-state parameter tables (batch x 2 * nslots amplitudes-typed values) or NULL.
 hipError_t launch_section(qsv_dtype dt, int r, int kmax, void *state, int n, int batch,
-                          DevPlanView pv, int sec, int c, size_t lds_bytes, const double *params,
-                          int n_params, hipStream_t s);
+                          DevPlanView pv, int sec, int c, size_t lds_bytes, const void *ptab,
+                          int nslots, hipStream_t s);
+// ptab[b][2 i], ptab[b][2 i + 1] for every parameterised op i (see OP_PROT / OP_PDIAG)
+hipError_t launch_param_table(qsv_dtype dt, const double *params, int n_params,
+                              const PSlot *slots, int nslots, int batch, void *ptab, hipStream_t s);
 // `hmats`: the plan's FP64 host table (diagonal entries are passed by value);
 // `dmats`: its device copy in the state's dtype (dense matrices are read there).
 hipError_t launch_pergate_host(qsv_dtype dt, void *state, int n, const PgOp &op, const cd *hmats,
@@ -51,5 +57,15 @@ hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, i
 hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,
                                 hipStream_t s);
 int reduce_blocks(int n);
+
+// adjoint.hip
+hipError_t launch_adjoint_section(qsv_dtype dt, int r, void *psi, void *lam, int n, int batch,
+                                  DevPlanView pv, int sec, int c, size_t lds, const void *ptab,
+                                  int nslots, double *part, hipStream_t s);
+hipError_t launch_apply_zsum(qsv_dtype dt, const void *psi, void *lam, int n, int batch,
+                             const qsv_zterm *terms, int nt, hipStream_t s);
+hipError_t launch_grad_reduce(const double *part, int nslots, int batch, uint64_t nchunks,
+                              double *ssum, const int32_t *off, const int32_t *slots, int nparams,
+                              double *grad, hipStream_t s);
 
 }  // namespace qsv

@@ -145,7 +145,51 @@ k_scale(V *__restrict__ st, int n, const double *__restrict__ norm2) {
     }
 }
 
+// Per-state parameter tables of the parameterised ops (see OP_PROT / OP_PDIAG):
+//   RX, RY: (cos(t/2), 0), (sin(t/2), 0);  RZ: e^{-i t/2}, e^{i t/2};  P: 1, e^{i t}
+template <typename V>
+__global__ void __launch_bounds__(256)
+k_param_table(const double *__restrict__ params, int n_params, const PSlot *__restrict__ slots,
+              int nslots, int batch, V *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nslots * batch) return;
+    const int b = i / nslots, k = i % nslots;
+    const PSlot ps = slots[k];
+    const double t = params[(size_t)b * n_params + ps.param];
+    double s, c;
+    V v0, v1;
+    if (ps.rot == ROT_RX || ps.rot == ROT_RY) {
+        sincos(0.5 * t, &s, &c);
+        v0.x = c; v0.y = 0;
+        v1.x = s; v1.y = 0;
+    } else if (ps.rot == ROT_RZ) {
+        sincos(0.5 * t, &s, &c);
+        v0.x = c; v0.y = -s;
+        v1.x = c; v1.y = s;
+    } else {
+        sincos(t, &s, &c);
+        v0.x = 1; v0.y = 0;
+        v1.x = c; v1.y = s;
+    }
+    out[(size_t)b * 2 * nslots + 2 * k] = v0;
+    out[(size_t)b * 2 * nslots + 2 * k + 1] = v1;
+}
+
 }  // namespace
+
+hipError_t launch_param_table(qsv_dtype dt, const double *params, int n_params,
+                              const PSlot *slots, int nslots, int batch, void *ptab, hipStream_t s) {
+    const int total = nslots * batch;
+    if (total == 0) return hipSuccess;
+    const int blocks = (total + 255) / 256;
+    if (dt == QSV_C128)
+        hipLaunchKernelGGL((k_param_table<Cplx<double>>), dim3(blocks), dim3(256), 0, s, params,
+                           n_params, slots, nslots, batch, (Cplx<double> *)ptab);
+    else
+        hipLaunchKernelGGL((k_param_table<Cplx<float>>), dim3(blocks), dim3(256), 0, s, params,
+                           n_params, slots, nslots, batch, (Cplx<float> *)ptab);
+    return hipGetLastError();
+}
 
 int reduce_blocks(int n) {
     uint64_t N = 1ull << n;

@@ -517,7 +517,7 @@ std::vector<POp> fuse(const std::vector<POp> &in, int f) {
         F.op.type = OP_DENSE;
         F.op.k = (uint8_t)pos.size();
         for (size_t t = 0; t < pos.size(); ++t) F.op.a[t] = (uint8_t)pos[t];
-        F.op.gate = in[i].op.gate;
+        F.op.slot = -1;
         F.m = std::move(M);
         F.fusable = true;
         F.regmask = mask;
@@ -656,7 +656,7 @@ static void lower_section(Plan &P, int si) {
             }
             POp o;
             std::memset(&o.op, 0, sizeof(o.op));
-            o.op.gate = idx;
+            o.op.slot = -1;
             if (g.is_swap) {
                 // relabel: the two positions exchange the qubits they stand for
                 int pa = q2pos[g.q[0]], pb = q2pos[g.q[1]];
@@ -671,6 +671,8 @@ static void lower_section(Plan &P, int si) {
                 o.op.rot = rk;
                 o.op.k = 1;
                 o.op.arg = g.param;
+                o.op.slot = (int32_t)P.n_param_ops;
+                P.pslots.push_back(PSlot{g.param, (int32_t)rk});
                 if (rk == ROT_RX || rk == ROT_RY) {
                     o.op.type = OP_PROT;
                     o.op.a[0] = (uint8_t)q2pos[g.q[0]];
@@ -873,6 +875,14 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     block_circuit(P);
     for (size_t s = 0; s < P.sections.size(); ++s) lower_section(P, (int)s);
     lower_per_gate(P);
+    P.poff.assign(P.n_params + 1, 0);
+    for (const PSlot &ps : P.pslots) P.poff[ps.param + 1]++;
+    for (int64_t q = 0; q < P.n_params; ++q) P.poff[q + 1] += P.poff[q];
+    P.plist.assign(P.pslots.size(), 0);
+    {
+        std::vector<int32_t> fill(P.poff.begin(), P.poff.end() - 1);
+        for (size_t k = 0; k < P.pslots.size(); ++k) P.plist[fill[P.pslots[k].param]++] = (int32_t)k;
+    }
     P.uid = g_plan_uid.fetch_add(1);
     return QSV_OK;
 }

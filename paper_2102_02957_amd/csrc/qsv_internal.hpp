@@ -34,8 +34,10 @@ enum OpType : uint8_t {
     OP_XREG = 2,    // Pauli X on register position a[0]: a register permutation
     OP_CX = 3,      // X on register position a[0] where bit source a[1] is 1
     OP_DIAG = 4,    // diagonal with 2^k entries mats[arg + sum_j bit(a[j]) << j]
-    OP_PROT = 5,    // parameterised RX/RY on register position a[0], angle params[arg]
-    OP_PDIAG = 6,   // parameterised RZ/P on bit source a[0], angle params[arg]
+    OP_PROT = 5,    // parameterised RX/RY on register position a[0]; (cos, sin) of half the
+                    // angle params[arg] precomputed at ptab[2 slot], ptab[2 slot + 1]
+    OP_PDIAG = 6,   // parameterised RZ/P on bit source a[0]; its two diagonal entries
+                    // precomputed at ptab[2 slot], ptab[2 slot + 1]
 };
 
 enum RotKind : uint8_t { ROT_RX = 1, ROT_RY = 2, ROT_RZ = 3, ROT_P = 4 };
@@ -45,8 +47,8 @@ struct DevOp {               // 16 bytes
     uint8_t k;
     uint8_t a[5];
     uint8_t rot;
-    int32_t arg;
-    int32_t gate;            // circuit gate index (first gate of a fused group), for the adjoint
+    int32_t arg;             // matrix offset (dense, diag) or parameter index (param ops)
+    int32_t slot;            // param ops: index into the per-state parameter table; else -1
 };
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
 
@@ -69,6 +71,12 @@ struct DevSection {          // 128 bytes
     uint8_t pad[48];
 };
 static_assert(sizeof(DevSection) == 128, "DevSection layout");
+
+// one parameterised op: which parameter drives it and how
+struct PSlot {
+    int32_t param;
+    int32_t rot;             // RotKind
+};
 
 // ---- per-gate path records ------------------------------------------------
 
@@ -129,6 +137,8 @@ struct Plan {
     std::vector<PgOp> pg;                   // per-gate path ops
     int64_t n_params = 0;
     int64_t n_param_ops = 0;                // parameterised ops over all sections
+    std::vector<PSlot> pslots;              // [n_param_ops]
+    std::vector<int32_t> poff, plist;       // CSR: the param ops driven by parameter p
     double flops = 0.0;
     int64_t chunk_swaps = 0;
     uint64_t uid = 0;                       // identity for device-side caching

@@ -16,6 +16,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "batch.hpp"
 #include "device.hpp"
 #include "qsv_internal.hpp"
 
@@ -39,6 +40,13 @@ struct DevPlanBuf {
     DevPlanView view{};
 };
 
+struct BatchEntry {
+    std::vector<uint64_t> uids, offsets;
+    void *states = nullptr;
+    double *norms = nullptr;
+    BatchLaunch launch;
+};
+
 struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<hipEvent_t> pool;
@@ -54,10 +62,13 @@ struct qsv_ctx {
     std::list<qsv::DevPlanBuf> plans;      // most recent first
     double *partials = nullptr;
     size_t partials_bytes = 0;
+    void *ptab = nullptr;                  // per-state parameter tables
+    size_t ptab_bytes = 0;
     qsv_zterm *terms = nullptr;
     size_t terms_cap = 0;
     bool timing = false;
     qsv::Timer timers[2];
+    std::list<qsv::BatchEntry> batches;    // prepared batch launches, most recent first
     std::mutex mu;
 };
 
@@ -93,7 +104,10 @@ qsv_status upload_plan(qsv_ctx *ctx, const Plan &P, const DevPlanView **out) {
     size_t o_op = align(o_ph + P.dphase.size() * sizeof(DevPhase));
     size_t o_m = align(o_op + P.dops.size() * sizeof(DevOp));
     size_t o_pg = align(o_m + P.dmats.size() * es);
-    size_t total = align(o_pg + P.pg.size() * sizeof(PgOp)) + 256;
+    size_t o_ps = align(o_pg + P.pg.size() * sizeof(PgOp));
+    size_t o_po = align(o_ps + P.pslots.size() * sizeof(PSlot));
+    size_t o_pl = align(o_po + P.poff.size() * sizeof(int32_t));
+    size_t total = align(o_pl + P.plist.size() * sizeof(int32_t)) + 256;
     std::vector<unsigned char> host(total, 0);
     std::memcpy(host.data() + o_sec, P.dsec.data(), P.dsec.size() * sizeof(DevSection));
     std::memcpy(host.data() + o_ph, P.dphase.data(), P.dphase.size() * sizeof(DevPhase));
@@ -108,6 +122,9 @@ qsv_status upload_plan(qsv_ctx *ctx, const Plan &P, const DevPlanView **out) {
         }
     }
     std::memcpy(host.data() + o_pg, P.pg.data(), P.pg.size() * sizeof(PgOp));
+    std::memcpy(host.data() + o_ps, P.pslots.data(), P.pslots.size() * sizeof(PSlot));
+    std::memcpy(host.data() + o_po, P.poff.data(), P.poff.size() * sizeof(int32_t));
+    std::memcpy(host.data() + o_pl, P.plist.data(), P.plist.size() * sizeof(int32_t));
     DevPlanBuf b;
     b.uid = P.uid;
     hipError_t e = hipMalloc(&b.block, total);
@@ -126,6 +143,9 @@ qsv_status upload_plan(qsv_ctx *ctx, const Plan &P, const DevPlanView **out) {
     b.view.ops = (const DevOp *)(base + o_op);
     b.view.mats = base + o_m;
     b.view.pg = (const PgOp *)(base + o_pg);
+    b.view.pslots = (const PSlot *)(base + o_ps);
+    b.view.poff = (const int32_t *)(base + o_po);
+    b.view.plist = (const int32_t *)(base + o_pl);
     ctx->plans.push_front(b);
     while (ctx->plans.size() > 64) {
         (void)hipFree(ctx->plans.back().block);
@@ -204,8 +224,23 @@ size_t section_lds(const Plan &P, int s) {
     return (size_t(1) << S.c) * amp_bytes(P.dtype);
 }
 
+qsv_status ensure_ptab(qsv_ctx *ctx, size_t bytes) {
+    if (ctx->ptab_bytes >= bytes) return QSV_OK;
+    if (ctx->ptab) (void)hipFree(ctx->ptab);
+    ctx->ptab = nullptr;
+    ctx->ptab_bytes = 0;
+    hipError_t e = hipMalloc(&ctx->ptab, bytes);
+    if (e != hipSuccess) {
+        set_error(std::string("parameter table workspace: ") + hipGetErrorString(e));
+        return QSV_E_NOMEM;
+    }
+    ctx->ptab_bytes = bytes;
+    return QSV_OK;
+}
+
+// ptab: per-state parameter tables already filled (or NULL for plans without parameters)
 qsv_status run_sections(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv, void *state, int n,
-                        int batch, int64_t s0, int64_t s1, const double *params, hipStream_t s) {
+                        int batch, int64_t s0, int64_t s1, const void *ptab, hipStream_t s) {
     const bool materialise = P.opt.swap_mode == QSV_SWAP_MATERIALIZE;
     for (int64_t si = s0; si < s1; ++si) {
         const HostSection &H = P.sections[si];
@@ -226,7 +261,7 @@ qsv_status run_sections(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv, void
         size_t lds = section_lds(P, (int)si);
         qsv_status rc = timed(ctx, 0, s, [&] {
             return launch_section(P.dtype, P.r, P.kmax, state, n, batch, pv, (int)si, P.c, lds,
-                                  params, (int)P.n_params, s);
+                                  ptab, (int)P.n_param_ops, s);
         }, "section launch");
         if (rc != QSV_OK) return rc;
     }
@@ -405,7 +440,9 @@ void qsv_destroy(qsv_ctx *ctx) {
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
         for (auto &b : ctx->plans) (void)hipFree(b.block);
+        for (auto &b : ctx->batches) batch_release(b.launch);
         if (ctx->partials) (void)hipFree(ctx->partials);
+        if (ctx->ptab) (void)hipFree(ctx->ptab);
         if (ctx->terms) (void)hipFree(ctx->terms);
         for (auto &t : ctx->timers) {
             for (auto &pr : t.pending) {
@@ -523,8 +560,14 @@ qsv_status qsv_apply_params(qsv_ctx *ctx, const qsv_plan *plan, void *states, in
     DeviceGuard g(ctx->device);
     const DevPlanView *pv = nullptr;
     if ((rc = upload_plan(ctx, P, &pv)) != QSV_OK) return rc;
-    return run_sections(ctx, P, *pv, states, n, batch, 0, (int64_t)P.sections.size(), params_dev,
-                        (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t es = amp_bytes(ctx->dtype);
+    if ((rc = ensure_ptab(ctx, (size_t)batch * 2 * std::max<int64_t>(1, P.n_param_ops) * es)) != QSV_OK)
+        return rc;
+    hipError_t e = launch_param_table(ctx->dtype, params_dev, (int)P.n_params, pv->pslots,
+                                      (int)P.n_param_ops, batch, ctx->ptab, s);
+    if (e != hipSuccess) return hip_fail(e, "parameter table launch");
+    return run_sections(ctx, P, *pv, states, n, batch, 0, (int64_t)P.sections.size(), ctx->ptab, s);
 }
 
 static qsv_status upload_terms(qsv_ctx *ctx, const qsv_zterm *terms, size_t nt, hipStream_t s) {
@@ -674,3 +717,147 @@ qsv_status qsv_timing_read(qsv_ctx *ctx, int which, double *total_ms, int64_t *l
 }  // extern "C"
 
 // placeholders replaced by adjoint.hip / batch.hip
+
+extern "C" qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *const *plans,
+                                    const uint64_t *offsets, void *states, double *norms_dev,
+                                    void *stream) {
+    if (!ctx || !plans || !offsets || !states || !norms_dev) {
+        set_error("qsv_batch_run: NULL argument");
+        return QSV_E_INVALID;
+    }
+    if (count < 1 || count > (1 << 20)) {
+        set_error("qsv_batch_run: count must be in [1, 2^20]");
+        return QSV_E_INVALID;
+    }
+    std::vector<const Plan *> ps(count);
+    std::vector<uint64_t> uids(count), offs(offsets, offsets + count);
+    for (int b = 0; b < count; ++b) {
+        if (!plans[b]) {
+            set_error("qsv_batch_run: NULL plan");
+            return QSV_E_INVALID;
+        }
+        ps[b] = &plans[b]->p;
+        uids[b] = ps[b]->uid;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    BatchEntry *hit = nullptr;
+    for (auto it = ctx->batches.begin(); it != ctx->batches.end(); ++it) {
+        if (it->uids == uids && it->offsets == offs && it->states == states &&
+            it->norms == norms_dev) {
+            ctx->batches.splice(ctx->batches.begin(), ctx->batches, it);
+            hit = &ctx->batches.front();
+            break;
+        }
+    }
+    if (!hit) {
+        BatchEntry e;
+        e.uids = uids;
+        e.offsets = offs;
+        e.states = states;
+        e.norms = norms_dev;
+        std::string err;
+        // spin limit of a dependency wait: ~2^24 sleeps of 2 x 64 cycles, about a second
+        qsv_status rc = batch_prepare(ctx->dtype, count, ps.data(), offsets, states, norms_dev,
+                                      e.launch, err, 1u << 24);
+        if (rc != QSV_OK) {
+            batch_release(e.launch);
+            set_error("qsv_batch_run: " + err);
+            return rc;
+        }
+        ctx->batches.push_front(std::move(e));
+        hit = &ctx->batches.front();
+        while (ctx->batches.size() > 8) {
+            batch_release(ctx->batches.back().launch);
+            ctx->batches.pop_back();
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    qsv_status rc = timed(ctx, 0, s, [&] { return batch_replay(hit->launch, s); }, "batch graph launch");
+    return rc;
+}
+
+extern "C" qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm *terms,
+                                       size_t n_terms, const double *params_dev, int batch,
+                                       void *psi_dev, void *lambda_dev, double *energy_dev,
+                                       double *grad_dev, void *stream) {
+    if (!ctx || !plan || !terms || !psi_dev || !lambda_dev || !energy_dev) {
+        set_error("qsv_adjoint_grad: NULL argument");
+        return QSV_E_INVALID;
+    }
+    const Plan &P = plan->p;
+    const int n = P.n;
+    qsv_status rc = check_state(ctx, psi_dev, n);
+    if (rc != QSV_OK) return rc;
+    if ((rc = check_state(ctx, lambda_dev, n)) != QSV_OK) return rc;
+    if ((rc = check_plan(ctx, plan, n)) != QSV_OK) return rc;
+    if (batch < 1 || batch > 65535) {
+        set_error("batch must be in [1, 65535]");
+        return QSV_E_INVALID;
+    }
+    if (P.n_params > 0 && (!params_dev || !grad_dev)) {
+        set_error("params_dev / grad_dev is NULL");
+        return QSV_E_INVALID;
+    }
+    if (n_terms == 0 || n_terms > 4096) {
+        set_error("n_terms must be in [1, 4096]");
+        return QSV_E_INVALID;
+    }
+    for (size_t t = 0; t < n_terms; ++t)
+        if (n < 64 && (terms[t].zmask >> n) != 0) {
+            set_error("Z-string acts on a qubit >= n");
+            return QSV_E_INVALID;
+        }
+    if (P.opt.swap_mode != QSV_SWAP_REMAP || P.kmax > 2 || P.c - P.r > 8 ||
+        (P.dtype == QSV_C128 && P.r > 4)) {
+        set_error("adjoint plans need remap mode, fusion of at most 2 qubits, "
+                  "chunk_bits - register_bits <= 8 and register_bits <= 4 (complex128)");
+        return QSV_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const DevPlanView *pv = nullptr;
+    if ((rc = upload_plan(ctx, P, &pv)) != QSV_OK) return rc;
+    const size_t es = amp_bytes(ctx->dtype);
+    const int nslots = (int)P.n_param_ops;
+    if ((rc = ensure_ptab(ctx, (size_t)batch * 2 * std::max(1, nslots) * es)) != QSV_OK) return rc;
+    hipError_t e = hipSuccess;
+    if (nslots > 0) {
+        e = launch_param_table(ctx->dtype, params_dev, (int)P.n_params, pv->pslots, nslots, batch,
+                               ctx->ptab, s);
+        if (e != hipSuccess) return hip_fail(e, "parameter table launch");
+    }
+    // forward
+    e = launch_fill_basis(ctx->dtype, psi_dev, n, batch, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    rc = run_sections(ctx, P, *pv, psi_dev, n, batch, 0, (int64_t)P.sections.size(), ctx->ptab, s);
+    if (rc != QSV_OK) return rc;
+    // energies and lambda = H psi
+    const int nblk = reduce_blocks(n);
+    const uint64_t nchunks = 1ull << (n - P.c);
+    const size_t part_doubles = std::max<size_t>((size_t)nblk * batch,
+                                                 (size_t)batch * nslots * nchunks + (size_t)batch * nslots);
+    if ((rc = ensure_partials(ctx, part_doubles * sizeof(double))) != QSV_OK) return rc;
+    if ((rc = upload_terms(ctx, terms, n_terms, s)) != QSV_OK) return rc;
+    e = launch_reduce(ctx->dtype, 2, psi_dev, nullptr, n, batch, ctx->terms, (int)n_terms,
+                      ctx->partials, nblk, energy_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    e = launch_apply_zsum(ctx->dtype, psi_dev, lambda_dev, n, batch, ctx->terms, (int)n_terms, s);
+    if (e != hipSuccess) return hip_fail(e, "observable launch");
+    if (nslots == 0) return QSV_OK;
+    // reverse sweep over the sections
+    double *part = ctx->partials;
+    double *ssum = ctx->partials + (size_t)batch * nslots * nchunks;
+    for (int64_t si = (int64_t)P.sections.size() - 1; si >= 0; --si) {
+        const size_t lds = section_lds(P, (int)si);
+        rc = timed(ctx, 0, s, [&] {
+            return launch_adjoint_section(P.dtype, P.r, psi_dev, lambda_dev, n, batch, *pv, (int)si,
+                                          P.c, lds, ctx->ptab, nslots, part, s);
+        }, "adjoint section launch");
+        if (rc != QSV_OK) return rc;
+    }
+    e = launch_grad_reduce(part, nslots, batch, nchunks, ssum, pv->poff, pv->plist,
+                           (int)P.n_params, grad_dev, s);
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "gradient reduction launch");
+}

@@ -110,6 +110,8 @@ __device__ __forceinline__ void dense_apply(V (&a)[1 << R], cptr<V> m) {
             static_for<D>([&](auto L) __attribute__((always_inline)) { acc = cfma(ldc(m + (ROW.value * D + L.value)), in[L.value], acc); });
             a[b | dep_pos<P...>(ROW.value)] = acc;
         });
+        // one amplitude group at a time: keeps the live temporaries to one group
+        __builtin_amdgcn_sched_barrier(0);
     });
 }
 
@@ -264,6 +266,14 @@ __device__ __forceinline__ void chunk_scatter(const V (&a)[1 << R], V *__restric
     });
 }
 
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// (the next chunk's prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // LDS transposition from position->slot map `from` to map `to`.  Threads with
 // active == false take part in the barriers only.
 template <typename V, int R>
@@ -280,7 +290,7 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
         bw[B.value] = 1u << from[B.value];
         br[B.value] = 1u << to[B.value];
     });
-    __syncthreads();
+    lds_barrier();
     if (active) {
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
             uint32_t j = tw;
@@ -290,7 +300,7 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
             lds[lds_swizzle<V>((int)j)] = a[I.value];
         });
     }
-    __syncthreads();
+    lds_barrier();
     if (active) {
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
             uint32_t j = tr;
@@ -308,7 +318,7 @@ template <typename T, int R, int KMAX>
 __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<DevOp> ops,
                                           uint32_t o_begin, uint32_t o_end,
                                           cptr<typename Amp<T>::V> mats,
-                                          const double *__restrict__ prm, uint32_t pbase,
+                                          cptr<typename Amp<T>::V> ptab, uint32_t pbase,
                                           uint64_t base) {
     using V = typename Amp<T>::V;
     constexpr int RA = 1 << R;
@@ -363,39 +373,19 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
                 });
             }
         } else if (type == OP_PROT) {
-            double sn, cs;
-            sincos(0.5 * prm[op->arg], &sn, &cs);
-            V c0, s0, ms;
-            c0.x = (T)cs;
-            c0.y = 0;
+            const V cs = ldc(ptab + 2 * op->slot), sn = ldc(ptab + 2 * op->slot + 1);
+            V ms;
             if (op->rot == ROT_RY) {
-                s0.x = (T)sn;
-                s0.y = 0;
-                ms.x = (T)-sn;
+                ms.x = -sn.x;
                 ms.y = 0;
-                dispatch1_val<V, R>(a, op->a[0], c0, ms, s0, c0);
+                dispatch1_val<V, R>(a, op->a[0], cs, ms, sn, cs);
             } else {  // RX: [[c, -i s], [-i s, c]]
                 ms.x = 0;
-                ms.y = (T)-sn;
-                dispatch1_val<V, R>(a, op->a[0], c0, ms, ms, c0);
+                ms.y = -sn.x;
+                dispatch1_val<V, R>(a, op->a[0], cs, ms, ms, cs);
             }
         } else if (type == OP_PDIAG) {
-            const double th = prm[op->arg];
-            double sn, cs;
-            V d0, d1;
-            if (op->rot == ROT_RZ) {
-                sincos(0.5 * th, &sn, &cs);
-                d0.x = (T)cs;
-                d0.y = (T)-sn;
-                d1.x = (T)cs;
-                d1.y = (T)sn;
-            } else {
-                sincos(th, &sn, &cs);
-                d0.x = 1;
-                d0.y = 0;
-                d1.x = (T)cs;
-                d1.y = (T)sn;
-            }
+            const V d0 = ldc(ptab + 2 * op->slot), d1 = ldc(ptab + 2 * op->slot + 1);
             const unsigned s0 = op->a[0];
             static_for<RA>([&](auto I) __attribute__((always_inline)) {
                 a[I.value] = cmul(sel(src_bit(s0, pbase | I.value, base) != 0, d1, d0), a[I.value]);
@@ -404,29 +394,85 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
     }
 }
 
+__device__ __forceinline__ uint64_t chunk_base(cptr<DevSection> S, uint64_t chunk) {
+    uint64_t base = 0;
+    for (uint32_t k = 0; k < S->n_nl; ++k) base |= ((chunk >> k) & 1ull) << S->nl_phys[k];
+    return base;
+}
+
+// All phases of one section on the registers of one chunk (no HBM traffic).
+template <typename T, int R, int KMAX>
+__device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cptr<DevPhase> ph,
+                                             int nph, cptr<DevOp> ops,
+                                             cptr<typename Amp<T>::V> mats,
+                                             cptr<typename Amp<T>::V> ptab, uint64_t base,
+                                             typename Amp<T>::V *lds, int TB, bool active) {
+    using V = typename Amp<T>::V;
+    const unsigned tid = threadIdx.x;
+    const uint32_t pbase = tid << R;
+    for (int p = 0; p < nph; ++p) {
+        const cptr<DevPhase> P = ph + p;
+        chunk_ops<T, R, KMAX>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
+        if (p + 1 < nph) chunk_transpose<V, R>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
+    }
+}
+
 // One chunk of one section, forward: gather, phases, scatter.
 template <typename T, int R, int KMAX>
 __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
                                           cptr<DevSection> S, cptr<DevPhase> phases,
                                           cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
-                                          const double *__restrict__ prm, uint64_t chunk,
+                                          cptr<typename Amp<T>::V> ptab, uint64_t chunk,
                                           typename Amp<T>::V *lds, bool active) {
     using V = typename Amp<T>::V;
     const int TB = (int)S->c - R;
     const unsigned tid = threadIdx.x;
-    uint64_t base = 0;
-    for (uint32_t k = 0; k < S->n_nl; ++k) base |= ((chunk >> k) & 1ull) << S->nl_phys[k];
+    const uint64_t base = chunk_base(S, chunk);
     const cptr<DevPhase> ph = phases + S->phase_begin;
     const int nph = (int)(S->phase_end - S->phase_begin);
-    const uint32_t pbase = tid << R;
     V a[1 << R];
     if (active) chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
-    for (int p = 0; p < nph; ++p) {
-        const cptr<DevPhase> P = ph + p;
-        chunk_ops<T, R, KMAX>(a, ops, P->op_begin, P->op_end, mats, prm, pbase, base);
-        if (p + 1 < nph) chunk_transpose<V, R>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
-    }
+    chunk_phases<T, R, KMAX>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
     if (active) chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
+}
+
+// sum over the thread's registers of |a|^2 in FP64
+template <typename V, int R> __device__ __forceinline__ double reg_norm2(const V (&a)[1 << R]) {
+    double s = 0.0;
+    static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+        s += (double)a[I.value].x * (double)a[I.value].x + (double)a[I.value].y * (double)a[I.value].y;
+    });
+    return s;
+}
+
+// Same as run_chunk, and also returns (in thread 0) the chunk's FP64 sum of
+// |a|^2 after the section, reduced in a fixed order through `red` (blockDim.x
+// doubles of LDS).
+template <typename T, int R, int KMAX>
+__device__ __forceinline__ double run_chunk_norm(typename Amp<T>::V *__restrict__ st,
+                                                 cptr<DevSection> S, cptr<DevPhase> phases,
+                                                 cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
+                                                 cptr<typename Amp<T>::V> ptab, uint64_t chunk,
+                                                 typename Amp<T>::V *lds, double *red, bool active) {
+    using V = typename Amp<T>::V;
+    const int TB = (int)S->c - R;
+    const unsigned tid = threadIdx.x;
+    const uint64_t base = chunk_base(S, chunk);
+    const cptr<DevPhase> ph = phases + S->phase_begin;
+    const int nph = (int)(S->phase_end - S->phase_begin);
+    V a[1 << R];
+    if (active) chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
+    chunk_phases<T, R, KMAX>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
+    if (active) chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
+    red[tid] = active ? reg_norm2<V, R>(a) : 0.0;
+    __syncthreads();
+    for (unsigned s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
 }
 
 }  // namespace sec

@@ -278,3 +278,13 @@ def test_invalid_calls(torch, ctxs):
     p2 = B.Plan(10, W.ghz(10), B.QSV_C128)
     with pytest.raises(B.QsvError):
         ctx.apply(p2, st, mode=7)
+
+
+def test_large_qv_pipelined_vs_oracle(torch, ctxs):
+    """23 qubits: enough chunks that the persistent, prefetching section
+    kernel runs (every resident workgroup walks several chunks)."""
+    n = 23
+    gates = W.quantum_volume(n, n, 4)
+    got, plan = run_gpu(torch, ctxs, n, gates, B.QSV_C128, chunk_bits=10, register_bits=4)
+    assert plan.stats()["n_sections"] > 1
+    assert_close(got, oracle.apply_circuit(n, gates), B.QSV_C128, "qv23")
