@@ -51,7 +51,8 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("section_kernel.hip", "device.hpp", "qsv_internal.hpp"):
+    for f in ("section_core.hpp", "section_kernels.hpp", "section_kernel.hip", "section_c128.hip",
+              "section_c64.hip", "device.hpp", "qsv_internal.hpp", "planner.cpp"):
         with open(os.path.join(ROOT, "paper_2102_02957_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -240,7 +241,8 @@ def main():
         "parity": parity,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_section<double,4>" if dt == B.QSV_C128 else "k_section<float,5>",
+            "kernel": "k_section<%s, %d, ...> (one launch per section)"
+                      % ("double" if dt == B.QSV_C128 else "float", st["register_bits"]),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -215,15 +215,39 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm 
 
 /* ---- batched trajectories ---------------------------------------------- */
 
-/* Run `count` independent circuits, each on its own state of n_b qubits stored
- * at states + offsets[b] amplitudes (offsets: host array, 256-byte aligned
- * starts), in one persistent launch: init |0>, every section of plans[b],
- * FP64 norm, renormalise.  norms_dev[b] receives <psi_b|psi_b> before the
- * renormalisation.  Every plan must have n_b <= its chunk_bits... or any size:
- * multi-section plans are ordered by per-state section counters. */
+/* Run `count` independent circuits (e.g. noisy trajectories with sampled Pauli
+ * insertions), each on its own state of n_b qubits stored at states + offsets[b]
+ * amplitudes (offsets: host array; states must not overlap and must start on 256-byte
+ * boundaries), in one launch: every state is set to |0>, one workgroup walks all
+ * sections and chunks of its plan (largest states first), accumulates the FP64 norm of
+ * the final state, and every state is rescaled by 1/sqrt(norm).  norms_dev[b] receives
+ * <psi_b|psi_b> before the rescale.  The sequence is captured into a HIP graph on the
+ * first call for a given (plans, offsets, states, norms_dev) and replayed afterwards.
+ * Plans: same dtype as the context, remap mode, no bound parameters, equal
+ * register_bits, chunk_bits - register_bits <= 8 (QSV_E_UNSUPPORTED otherwise). */
 qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *const *plans,
                          const uint64_t *offsets, void *states, double *norms_dev,
                          void *stream);
+
+/* ---- autotuning -------------------------------------------------------- */
+
+/* Time `n_cands` option sets on the circuit (n, g, ng): for each, plan, run one
+ * untimed blocked apply on `state` (a caller-owned scratch of 2^n amplitudes of the
+ * context's dtype, overwritten), then `reps` timed applies between HIP events on
+ * `stream`.  *best = index of the fastest candidate; ms_out[k] (host, may be NULL) =
+ * mean milliseconds per apply, +inf for candidates that cannot be planned.  Chooses
+ * chunk_bits, pinned_low_bits, fusion_max_qubits and register_bits for the caller's
+ * own workload (the paper's chunk size nc, Sec. III-B, is a free parameter). */
+qsv_status qsv_autotune(qsv_ctx *ctx, qsv_dtype dt, int n, const qsv_gate *g, size_t ng,
+                        const qsv_options *cands, int n_cands, void *state, int reps, void *stream,
+                        int *best, double *ms_out);
+/* The same for a batch of circuits run through qsv_batch_run (ns[b], gates[b], ngs[b],
+ * offsets[b] as there; states / norms_dev are overwritten). */
+qsv_status qsv_autotune_batch(qsv_ctx *ctx, qsv_dtype dt, int count, const int *ns,
+                              const qsv_gate *const *gates, const size_t *ngs,
+                              const uint64_t *offsets, const qsv_options *cands, int n_cands,
+                              void *states, double *norms_dev, int reps, void *stream, int *best,
+                              double *ms_out);
 
 /* ---- timing (in-library HIP events around each launch) ------------------ */
 

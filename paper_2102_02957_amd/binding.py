@@ -70,7 +70,7 @@ EXPORTED = [
     "qsv_plan_export", "qsv_create", "qsv_destroy", "qsv_last_error", "qsv_init_basis",
     "qsv_apply_circuit", "qsv_apply_sections", "qsv_apply_params", "qsv_norm", "qsv_overlap",
     "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
-    "qsv_timing_enable", "qsv_timing_read",
+    "qsv_timing_enable", "qsv_timing_read", "qsv_autotune", "qsv_autotune_batch",
 ]
 
 _lib = None
@@ -109,6 +109,11 @@ def lib():
         "qsv_batch_run": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(U64), P, P, P]),
         "qsv_timing_enable": (I, [P, I]),
         "qsv_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), I]),
+        "qsv_autotune": (I, [P, I, I, ctypes.POINTER(Gate), SZ, ctypes.POINTER(Options), I, P, I, P,
+                             ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "qsv_autotune_batch": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.POINTER(Gate)),
+                                   ctypes.POINTER(SZ), ctypes.POINTER(U64), ctypes.POINTER(Options),
+                                   I, P, P, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(L, name)
@@ -402,3 +407,68 @@ def adjoint_energy_function():
             return ge[:, None] * g, None, None, None
 
     return AdjointEnergy
+
+
+def default_candidates(dtype, n):
+    """A small grid around the defaults: chunk bits, pinned low bits, fusion width."""
+    base = default_options(dtype)
+    out = []
+    for dc in (-1, 0):
+        for L in (2, 3, 4):
+            for f in (0, 2):
+                c = min(base.chunk_bits + dc, n)
+                out.append(dict(chunk_bits=c, pinned_low_bits=min(L, max(0, c - 2)),
+                                fusion_max_qubits=f, register_bits=min(base.register_bits, c)))
+    return out
+
+
+def _options_array(dtype, cands):
+    arr = (Options * len(cands))()
+    for i, kw in enumerate(cands):
+        arr[i] = make_options(dtype, **kw)
+    return arr
+
+
+def _autotune(self, n, gates, candidates=None, reps=2, scratch=None, stream=None):
+    """qsv_autotune: returns (best option dict, per-candidate ms)."""
+    torch = _torch()
+    cands = candidates or default_candidates(self.dtype, n)
+    arr = _options_array(self.dtype, cands)
+    g, keep = gates_to_c(gates)
+    tdt = torch.complex128 if self.dtype == QSV_C128 else torch.complex64
+    st = torch.empty(1 << n, dtype=tdt, device="cuda") if scratch is None else scratch
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * len(cands))()
+    _check(lib().qsv_autotune(self._h, self.dtype, n, g, len(gates), arr, len(cands), _ptr(st),
+                              int(reps), _stream(stream), ctypes.byref(best), ms))
+    del keep
+    return cands[best.value], list(ms)
+
+
+def _autotune_batch(self, circuits, offsets, states, candidates=None, reps=2, stream=None):
+    """qsv_autotune_batch over (n, gates) circuits packed at `offsets` in `states`."""
+    torch = _torch()
+    cands = candidates or [c for c in default_candidates(self.dtype, 64) if c["chunk_bits"] <= 64]
+    arr = _options_array(self.dtype, cands)
+    count = len(circuits)
+    ns = (ctypes.c_int * count)(*[n for n, _ in circuits])
+    gl, keep, ngs = [], [], (ctypes.c_size_t * count)()
+    for i, (_, gates) in enumerate(circuits):
+        g, k = gates_to_c(gates)
+        gl.append(g)
+        keep.append(k)
+        ngs[i] = len(gates)
+    gp = (ctypes.POINTER(Gate) * count)(*[ctypes.cast(g, ctypes.POINTER(Gate)) for g in gl])
+    offs = (ctypes.c_uint64 * count)(*[int(o) for o in offsets])
+    norms = torch.empty(count, dtype=torch.float64, device=states.device)
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * len(cands))()
+    _check(lib().qsv_autotune_batch(self._h, self.dtype, count, ns, gp, ngs, offs, arr, len(cands),
+                                    _ptr(states), _ptr(norms), int(reps), _stream(stream),
+                                    ctypes.byref(best), ms))
+    del keep, gl
+    return cands[best.value], list(ms)
+
+
+Context.autotune = _autotune
+Context.autotune_batch = _autotune_batch

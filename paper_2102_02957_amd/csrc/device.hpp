@@ -33,9 +33,10 @@ struct DevPlanView {           // device pointers of one uploaded plan
 // lds_bytes == 0 when the section has a single phase.
 // kmax: widest dense op in the plan (selects the kernel instance); ptab: the
 // per-state parameter tables (batch x 2 * nslots amplitudes-typed values) or NULL.
-hipError_t launch_section(qsv_dtype dt, int r, int kmax, void *state, int n, int batch,
-                          DevPlanView pv, int sec, int c, size_t lds_bytes, const void *ptab,
-                          int nslots, hipStream_t s);
+// dense_only: the section's flags carry SEC_DENSE_ONLY (a leaner kernel instance).
+hipError_t launch_section(qsv_dtype dt, int r, int kmax, bool dense_only, void *state, int n,
+                          int batch, DevPlanView pv, int sec, int c, size_t lds_bytes,
+                          const void *ptab, int nslots, hipStream_t s);
 // ptab[b][2 i], ptab[b][2 i + 1] for every parameterised op i (see OP_PROT / OP_PDIAG)
 hipError_t launch_param_table(qsv_dtype dt, const double *params, int n_params,
                               const PSlot *slots, int nslots, int batch, void *ptab, hipStream_t s);

@@ -751,6 +751,11 @@ static void lower_section(Plan &P, int si) {
         P.dphase.push_back(cur);
     }
     ds.phase_end = (uint32_t)P.dphase.size();
+    bool dense_only = true;
+    for (uint32_t ph = ds.phase_begin; ph < ds.phase_end; ++ph)
+        for (uint32_t o = P.dphase[ph].op_begin; o < P.dphase[ph].op_end; ++o)
+            if (P.dops[o].type != OP_DENSE) dense_only = false;
+    ds.flags = dense_only ? SEC_DENSE_ONLY : 0u;
     P.dsec.push_back(ds);
 }
 
@@ -860,8 +865,8 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         err = "a gate acts on more qubits than the chunk holds";
         return QSV_E_INVALID;
     }
-    if (P.c - P.r > 10) {
-        err = "chunk_bits - register_bits must be <= 10 (1024 threads per workgroup)";
+    if (P.c - P.r > 8) {
+        err = "chunk_bits - register_bits must be <= 8 (256 threads per workgroup)";
         return QSV_E_INVALID;
     }
     int maxlocal = 1;

@@ -68,8 +68,10 @@ struct DevSection {          // 128 bytes
     uint32_t c;              // chunk bits of this section
     uint32_t n_params_used;  // parameterised ops in this section
     uint32_t param_slot;     // first adjoint partial slot of this section
-    uint8_t pad[48];
+    uint32_t flags;          // SEC_DENSE_ONLY: every op is OP_DENSE
+    uint8_t pad[44];
 };
+constexpr uint32_t SEC_DENSE_ONLY = 1;
 static_assert(sizeof(DevSection) == 128, "DevSection layout");
 
 // one parameterised op: which parameter drives it and how

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <list>
 #include <memory>
@@ -258,10 +259,11 @@ qsv_status run_sections(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv, void
                 if (rc != QSV_OK) return rc;
             }
         }
-        size_t lds = section_lds(P, (int)si);
+        const size_t lds = section_lds(P, (int)si);
+        const bool dense_only = (P.dsec[si].flags & SEC_DENSE_ONLY) != 0;
         qsv_status rc = timed(ctx, 0, s, [&] {
-            return launch_section(P.dtype, P.r, P.kmax, state, n, batch, pv, (int)si, P.c, lds,
-                                  ptab, (int)P.n_param_ops, s);
+            return launch_section(P.dtype, P.r, P.kmax, dense_only, state, n, batch, pv, (int)si,
+                                  P.c, lds, ptab, (int)P.n_param_ops, s);
         }, "section launch");
         if (rc != QSV_OK) return rc;
     }
@@ -757,9 +759,8 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *con
         e.states = states;
         e.norms = norms_dev;
         std::string err;
-        // spin limit of a dependency wait: ~2^24 sleeps of 2 x 64 cycles, about a second
         qsv_status rc = batch_prepare(ctx->dtype, count, ps.data(), offsets, states, norms_dev,
-                                      e.launch, err, 1u << 24);
+                                      e.launch, err);
         if (rc != QSV_OK) {
             batch_release(e.launch);
             set_error("qsv_batch_run: " + err);

@@ -314,7 +314,7 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
 
 // Forward application of the ops [o_begin, o_end) of one phase to the
 // registers.  pbase = thread index << R; base = the chunk's physical base index.
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false>
 __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<DevOp> ops,
                                           uint32_t o_begin, uint32_t o_end,
                                           cptr<typename Amp<T>::V> mats,
@@ -339,6 +339,8 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
                     }
                 }
             }
+        } else if constexpr (DENSE_ONLY) {
+            // sections flagged dense-only carry no other op
         } else if (type == OP_XREG) {
             dispatch_cx<V, R>(a, op->a[0], false, 0, pbase, 0);
         } else if (type == OP_CX) {
@@ -401,7 +403,7 @@ __device__ __forceinline__ uint64_t chunk_base(cptr<DevSection> S, uint64_t chun
 }
 
 // All phases of one section on the registers of one chunk (no HBM traffic).
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false>
 __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cptr<DevPhase> ph,
                                              int nph, cptr<DevOp> ops,
                                              cptr<typename Amp<T>::V> mats,
@@ -412,13 +414,14 @@ __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cp
     const uint32_t pbase = tid << R;
     for (int p = 0; p < nph; ++p) {
         const cptr<DevPhase> P = ph + p;
-        chunk_ops<T, R, KMAX>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
-        if (p + 1 < nph) chunk_transpose<V, R>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
+        chunk_ops<T, R, KMAX, DENSE_ONLY>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
+        if (p + 1 < nph)
+            chunk_transpose<V, R>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
     }
 }
 
 // One chunk of one section, forward: gather, phases, scatter.
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false>
 __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
                                           cptr<DevSection> S, cptr<DevPhase> phases,
                                           cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
@@ -432,7 +435,7 @@ __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
     if (active) chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
-    chunk_phases<T, R, KMAX>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
+    chunk_phases<T, R, KMAX, DENSE_ONLY>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
     if (active) chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
 }
 

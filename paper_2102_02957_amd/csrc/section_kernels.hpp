@@ -28,7 +28,7 @@ using namespace sec;
 
 // KMAX: widest dense op the kernel instance carries code for (register pressure
 // of the whole kernel follows the widest case, so narrow plans use KMAX = 2).
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool DENSE_ONLY>
 __global__ void __launch_bounds__(256)
 k_section(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__restrict__ secs_g,
           int sec, const DevPhase *__restrict__ phases_g, const DevOp *__restrict__ ops_g,
@@ -38,7 +38,7 @@ k_section(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__res
     extern __shared__ unsigned char lds_raw[];
     V *st = state + ((uint64_t)blockIdx.y << n);
     const cptr<V> ptab = (cptr<V>)ptab_g + (size_t)blockIdx.y * 2 * nslots;
-    run_chunk<T, R, KMAX>(st, (cptr<DevSection>)secs_g + sec, (cptr<DevPhase>)phases_g,
+    run_chunk<T, R, KMAX, DENSE_ONLY>(st, (cptr<DevSection>)secs_g + sec, (cptr<DevPhase>)phases_g,
                           (cptr<DevOp>)ops_g, (cptr<V>)mats_g, ptab, blockIdx.x,
                           reinterpret_cast<V *>(lds_raw), true);
 }
@@ -49,7 +49,7 @@ k_section(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__res
 // (barriers inside the phases order LDS only).  Workgroups are spread over
 // the 8 XCDs so that one XCD streams a contiguous range of chunk ids
 // (neighbouring chunks share cache lines when few low bits are pinned).
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool DENSE_ONLY>
 __global__ void __launch_bounds__(256)
 k_section_pipe(typename Amp<T>::V *__restrict__ state, int n,
                const DevSection *__restrict__ secs_g, int sec,
@@ -87,7 +87,7 @@ k_section_pipe(typename Amp<T>::V *__restrict__ state, int n,
             base_n = chunk_base(S, gn);
             chunk_gather<V, R>(nx, st, S, ph[0].rd, base_n, tid, TB);
         }
-        chunk_phases<T, R, KMAX>(a, ph, nph, ops, mats, ptab, base, lds, TB, true);
+        chunk_phases<T, R, KMAX, DENSE_ONLY>(a, ph, nph, ops, mats, ptab, base, lds, TB, true);
         chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
         if (!more) break;
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) { a[I.value] = nx[I.value]; });
@@ -97,19 +97,21 @@ k_section_pipe(typename Amp<T>::V *__restrict__ state, int n,
     }
 }
 
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool DENSE_ONLY>
 inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv, int sec, int c,
                                    size_t lds_bytes, const void *ptab, int nslots,
                                    hipStream_t s) {
     using V = typename Amp<T>::V;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_section<T, R, KMAX>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_section<T, R, KMAX, DENSE_ONLY>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void *)k_section_pipe<T, R, KMAX>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
+        if constexpr (R >= 4 && KMAX == 2) {
+            e = hipFuncSetAttribute((const void *)k_section_pipe<T, R, KMAX, DENSE_ONLY>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
         attr_set = true;
     }
     if (c - R > 8 || c < R) return hipErrorInvalidConfiguration;
@@ -118,16 +120,19 @@ inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv
     // persistent pipelined kernel when every resident workgroup gets >= 2 chunks
     static int resident = -1;
     static size_t resident_lds = (size_t)-1;
-    if (resident < 0 || resident_lds != lds_bytes) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_section_pipe<T, R, KMAX>,
-                                                         (int)block.x, lds_bytes) != hipSuccess)
-            per_cu = 0;
-        int dev = 0, cus = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        resident = per_cu * cus;
-        resident_lds = lds_bytes;
+    if constexpr (R >= 4 && KMAX == 2) {
+        if (resident < 0 || resident_lds != lds_bytes) {
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, k_section_pipe<T, R, KMAX, DENSE_ONLY>, (int)block.x, lds_bytes) !=
+                hipSuccess)
+                per_cu = 0;
+            int dev = 0, cus = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            resident = per_cu * cus;
+            resident_lds = lds_bytes;
+        }
     }
     const uint64_t G = ((uint64_t)resident / 8) * 8;
     // the prefetching variant needs twice the amplitude registers, which halves
@@ -136,31 +141,39 @@ inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv
         const char *e = getenv("QSV_SECTION_PIPE");
         return e && e[0] == '1';
     }();
-    if (pipe_on && batch == 1 && G >= 8 && nchunks >= 2 * G && nchunks % 8 == 0) {
-        hipLaunchKernelGGL((k_section_pipe<T, R, KMAX>), dim3((unsigned)G, 1), block, lds_bytes, s,
+    if constexpr (R >= 4 && KMAX == 2) {
+      if (pipe_on && batch == 1 && G >= 8 && nchunks >= 2 * G && nchunks % 8 == 0) {
+        hipLaunchKernelGGL((k_section_pipe<T, R, KMAX, DENSE_ONLY>), dim3((unsigned)G, 1), block, lds_bytes, s,
                            (V *)state, n, pv.secs, sec, pv.phases, pv.ops, (const V *)pv.mats,
                            (const V *)ptab, nslots, nchunks);
         return hipGetLastError();
+      }
     }
     dim3 grid((unsigned)nchunks, (unsigned)batch);
-    hipLaunchKernelGGL((k_section<T, R, KMAX>), grid, block, lds_bytes, s, (V *)state, n, pv.secs,
+    hipLaunchKernelGGL((k_section<T, R, KMAX, DENSE_ONLY>), grid, block, lds_bytes, s, (V *)state, n, pv.secs,
                        sec, pv.phases, pv.ops, (const V *)pv.mats, (const V *)ptab, nslots);
     return hipGetLastError();
 }
 
 template <typename T>
-inline hipError_t launch_section_dt(int r, int kmax, void *state, int n, int batch, DevPlanView pv,
-                                    int sec, int c, size_t lds_bytes, const void *ptab,
-                                    int nslots, hipStream_t s) {
-#define QSV_SEC(R_, K_) \
-    return launch_section_t<T, R_, K_>(state, n, batch, pv, sec, c, lds_bytes, ptab, nslots, s)
+inline hipError_t launch_section_dt(int r, int kmax, bool dense_only, void *state, int n, int batch,
+                                    DevPlanView pv, int sec, int c, size_t lds_bytes,
+                                    const void *ptab, int nslots, hipStream_t s) {
+#define QSV_SEC(R_, K_, D_)                                                                  \
+    return launch_section_t<T, R_, K_, D_>(state, n, batch, pv, sec, c, lds_bytes, ptab, nslots, s)
     const bool wide = kmax > 2;
     switch (r) {
-        case 1: QSV_SEC(1, 1);
-        case 2: QSV_SEC(2, 2);
-        case 3: if (wide) QSV_SEC(3, 3); else QSV_SEC(3, 2);
-        case 4: if (wide) QSV_SEC(4, 4); else QSV_SEC(4, 2);
-        case 5: if (wide) QSV_SEC(5, 5); else QSV_SEC(5, 2);
+        case 1: QSV_SEC(1, 1, false);
+        case 2: QSV_SEC(2, 2, false);
+        case 3: if (wide) QSV_SEC(3, 3, false); else QSV_SEC(3, 2, false);
+        case 4:
+            if (wide) QSV_SEC(4, 4, false);
+            else if (dense_only) QSV_SEC(4, 2, true);
+            else QSV_SEC(4, 2, false);
+        case 5:
+            if (wide) QSV_SEC(5, 5, false);
+            else if (dense_only) QSV_SEC(5, 2, true);
+            else QSV_SEC(5, 2, false);
     }
 #undef QSV_SEC
     return hipErrorInvalidValue;

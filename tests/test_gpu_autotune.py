@@ -1,0 +1,71 @@
+"""GPU tests of the autotuner: it times every candidate, reports the planner's
+rejections as +inf, and the option set it returns gives a plan that still
+matches the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2102_02957_amd import binding as B
+from paper_2102_02957_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def test_autotune_single_state(torch):
+    n = 16
+    gates = W.quantum_volume(n, 6, 2)
+    ctx = B.Context(B.QSV_C128)
+    cands = [
+        dict(chunk_bits=10, pinned_low_bits=2, fusion_max_qubits=2, register_bits=4),
+        dict(chunk_bits=12, pinned_low_bits=3, fusion_max_qubits=2, register_bits=4),
+        # 2^(13-3) threads per workgroup: more than the kernels take, rejected
+        dict(chunk_bits=13, pinned_low_bits=3, fusion_max_qubits=2, register_bits=3),
+        dict(chunk_bits=11, pinned_low_bits=3, fusion_max_qubits=0, register_bits=3),
+    ]
+    best, ms = ctx.autotune(n, gates, candidates=cands, reps=2)
+    assert len(ms) == len(cands)
+    assert math.isinf(ms[2])
+    assert all(math.isfinite(ms[k]) and ms[k] > 0 for k in (0, 1, 3))
+    assert best == cands[int(np.argmin(ms))]
+    plan = B.Plan(n, gates, B.QSV_C128, **best)
+    st = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    ctx.init_basis(st, n, 0)
+    ctx.apply(plan, st)
+    got = st.cpu().numpy()
+    assert 1.0 - oracle.fidelity(got, oracle.apply_circuit(n, gates)) < 1e-12
+
+
+def test_autotune_batch(torch):
+    trajs = W.noisy_trajectories(12, 8, 13, 6, 0.02, 4)
+    offs, o = [], 0
+    for n, _ in trajs:
+        offs.append(o)
+        o += 1 << n
+    states = torch.empty(o, dtype=torch.complex64, device="cuda")
+    ctx = B.Context(B.QSV_C64)
+    cands = [
+        dict(chunk_bits=10, pinned_low_bits=2, fusion_max_qubits=2, register_bits=4),
+        dict(chunk_bits=12, pinned_low_bits=3, fusion_max_qubits=2, register_bits=5),
+    ]
+    best, ms = ctx.autotune_batch(trajs, offs, states, candidates=cands, reps=2)
+    assert all(math.isfinite(m) and m > 0 for m in ms)
+    assert best == cands[int(np.argmin(ms))]
+    plans = [B.Plan(n, g, B.QSV_C64, **best) for n, g in trajs]
+    norms = ctx.batch_run(plans, offs, states)
+    torch.cuda.synchronize()
+    host = states.cpu().numpy().astype(np.complex128)
+    assert np.all(np.abs(norms.cpu().numpy() - 1.0) < 2e-5)
+    for b, (n, gates) in enumerate(trajs):
+        got = host[offs[b]:offs[b] + (1 << n)]
+        assert 1.0 - oracle.fidelity(got, oracle.apply_circuit(n, gates)) < 1e-5, b

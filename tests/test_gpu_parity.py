@@ -280,9 +280,9 @@ def test_invalid_calls(torch, ctxs):
         ctx.apply(p2, st, mode=7)
 
 
-def test_large_qv_pipelined_vs_oracle(torch, ctxs):
-    """23 qubits: enough chunks that the persistent, prefetching section
-    kernel runs (every resident workgroup walks several chunks)."""
+def test_large_qv_vs_oracle(torch, ctxs):
+    """23 qubits at chunk 10: 8192 chunks per section, more workgroups than
+    the device holds at once."""
     n = 23
     gates = W.quantum_volume(n, n, 4)
     got, plan = run_gpu(torch, ctxs, n, gates, B.QSV_C128, chunk_bits=10, register_bits=4)

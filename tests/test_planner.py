@@ -46,7 +46,7 @@ CASES = [
 def test_plan_equals_circuit(name, builder, n, c, mode):
     gates = builder(n, 3)
     st, ops = plan_matches_circuit(n, gates, chunk_bits=c, swap_mode=mode,
-                                   register_bits=min(3, c), pinned_low_bits=min(1, c - 3) if c > 3 else 0)
+                                   register_bits=min(4, c), pinned_low_bits=min(1, c - 3) if c > 3 else 0)
     assert st["n_sections"] >= 1
     if n <= c:
         assert st["n_sections"] == 1
@@ -160,6 +160,9 @@ def test_invalid_options_rejected():
         B.Plan(35, [], B.QSV_C128)
     with pytest.raises(B.QsvError):
         B.Plan(20, W.ghz(20), 3)
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(20, W.ghz(20), B.QSV_C128, chunk_bits=13, register_bits=3)
+    assert "256 threads" in str(e.value)
 
 
 def test_empty_circuit():
