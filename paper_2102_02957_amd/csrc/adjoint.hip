@@ -91,50 +91,52 @@ __device__ __forceinline__ double dgrad1_dispatch(const V (&psi)[1 << R], const 
 
 // inverse of one forward op, applied to the registers
 template <typename T, int R, int KMAX>
-__device__ __forceinline__ void op_inverse(typename Amp<T>::V (&a)[1 << R], cptr<DevOp> op,
+__device__ __forceinline__ void op_inverse(typename Amp<T>::V (&a)[1 << R], const OpH &op,
                                            cptr<typename Amp<T>::V> mats,
                                            cptr<typename Amp<T>::V> ptab, uint32_t pbase,
                                            uint64_t base) {
     using V = typename Amp<T>::V;
     constexpr int RA = 1 << R;
-    const uint32_t type = op->type, k = op->k;
+    const uint32_t type = op.type, k = op.k;
     if (type == OP_DENSE) {
-        const cptr<V> m = mats + op->arg;
-        if (k == 1) adj1<V, R>(a, op->a[0], m);
-        else adj2<V, R>(a, op->a[0], op->a[1], m);
+        const cptr<V> m = mats + op.arg;
+        if (k == 1) adj1<V, R>(a, op.a[0], m);
+        else adj2<V, R>(a, op.a[0], op.a[1], m);
     } else if (type == OP_XREG) {
-        dispatch_cx<V, R>(a, op->a[0], false, 0, pbase, 0);
+        dispatch_cx<V, R>(a, op.a[0], false, 0, pbase, 0);
     } else if (type == OP_CX) {
-        const unsigned s = op->a[1];
+        const unsigned s = op.a[1];
         const unsigned gbit = s >= SRC_GLOBAL ? (unsigned)((base >> (s - SRC_GLOBAL)) & 1ull) : 0u;
-        dispatch_cx<V, R>(a, op->a[0], true, s, pbase, gbit);
+        dispatch_cx<V, R>(a, op.a[0], true, s, pbase, gbit);
     } else if (type == OP_DIAG) {
-        const cptr<V> tab = mats + op->arg;
+        const cptr<V> tab = mats + op.arg;
         static_for<RA>([&](auto I) __attribute__((always_inline)) {
             unsigned idx = 0;
-            for (uint32_t j = 0; j < k; ++j) idx |= src_bit(op->a[j], pbase | I.value, base) << j;
+            static_for<5>([&](auto J) __attribute__((always_inline)) {
+                if (J.value < k) idx |= src_bit(op.a[J.value], pbase | I.value, base) << J.value;
+            });
             V d = ldc(tab + idx);
             d.y = -d.y;
             a[I.value] = cmul(d, a[I.value]);
         });
     } else if (type == OP_PROT) {
-        const V cs = ldc(ptab + 2 * op->slot), sn = ldc(ptab + 2 * op->slot + 1);
+        const V cs = ldc(ptab + 2 * op.slot), sn = ldc(ptab + 2 * op.slot + 1);
         V ms;
-        if (op->rot == ROT_RY) {  // RY(-t) = [[c, s], [-s, c]]
+        if (op.rot == ROT_RY) {  // RY(-t) = [[c, s], [-s, c]]
             ms.x = -sn.x;
             ms.y = 0;
-            dispatch1_val<V, R>(a, op->a[0], cs, sn, ms, cs);
+            dispatch1_val<V, R>(a, op.a[0], cs, sn, ms, cs);
         } else {  // RX(-t) = [[c, i s], [i s, c]]
             V is;
             is.x = 0;
             is.y = sn.x;
-            dispatch1_val<V, R>(a, op->a[0], cs, is, is, cs);
+            dispatch1_val<V, R>(a, op.a[0], cs, is, is, cs);
         }
     } else if (type == OP_PDIAG) {
-        V d0 = ldc(ptab + 2 * op->slot), d1 = ldc(ptab + 2 * op->slot + 1);
+        V d0 = ldc(ptab + 2 * op.slot), d1 = ldc(ptab + 2 * op.slot + 1);
         d0.y = -d0.y;
         d1.y = -d1.y;
-        const unsigned s0 = op->a[0];
+        const unsigned s0 = op.a[0];
         static_for<RA>([&](auto I) __attribute__((always_inline)) {
             a[I.value] = cmul(sel(src_bit(s0, pbase | I.value, base) != 0, d1, d0), a[I.value]);
         });
@@ -145,37 +147,37 @@ __device__ __forceinline__ void op_inverse(typename Amp<T>::V (&a)[1 << R], cptr
 // 2 Re <lam| dU |psi> over the thread's registers for a parameterised op
 template <typename T, int R>
 __device__ __forceinline__ double op_dgrad(const typename Amp<T>::V (&psi)[1 << R],
-                                           const typename Amp<T>::V (&lam)[1 << R], cptr<DevOp> op,
+                                           const typename Amp<T>::V (&lam)[1 << R], const OpH &op,
                                            cptr<typename Amp<T>::V> ptab, uint32_t pbase,
                                            uint64_t base) {
     using V = typename Amp<T>::V;
     constexpr int RA = 1 << R;
-    const V t0 = ldc(ptab + 2 * op->slot), t1 = ldc(ptab + 2 * op->slot + 1);
-    if (op->type == OP_PROT) {
+    const V t0 = ldc(ptab + 2 * op.slot), t1 = ldc(ptab + 2 * op.slot + 1);
+    if (op.type == OP_PROT) {
         // RY: dU = 1/2 [[-s, -c], [c, -s]];  RX: dU = 1/2 [[-s, -i c], [-i c, -s]]
         const T c = t0.x * (T)0.5, s = t1.x * (T)0.5;
         V ms, d01, d10;
         ms.x = -s;
         ms.y = 0;
-        if (op->rot == ROT_RY) {
+        if (op.rot == ROT_RY) {
             d01.x = -c; d01.y = 0;
             d10.x = c;  d10.y = 0;
         } else {
             d01.x = 0; d01.y = -c;
             d10 = d01;
         }
-        return dgrad1_dispatch<V, R>(psi, lam, op->a[0], ms, d01, d10, ms);
+        return dgrad1_dispatch<V, R>(psi, lam, op.a[0], ms, d01, d10, ms);
     }
     // RZ: dU = diag(-i/2 d0, i/2 d1);  P: dU = diag(0, i d1)
     V e0, e1;
-    if (op->rot == ROT_RZ) {
+    if (op.rot == ROT_RZ) {
         e0.x = (T)0.5 * t0.y;  e0.y = (T)-0.5 * t0.x;
         e1.x = (T)-0.5 * t1.y; e1.y = (T)0.5 * t1.x;
     } else {
         e0.x = 0; e0.y = 0;
         e1.x = -t1.y; e1.y = t1.x;
     }
-    const unsigned s0 = op->a[0];
+    const unsigned s0 = op.a[0];
     double acc = 0.0;
     static_for<RA>([&](auto I) __attribute__((always_inline)) {
         const V v = cmul(sel(src_bit(s0, pbase | I.value, base) != 0, e1, e0), psi[I.value]);
@@ -223,14 +225,14 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
     const int nwaves = (int)(blockDim.x + 63) / 64;
 
     V psi[1 << R], lam[1 << R];
-    chunk_gather<V, R>(psi, psi_st, S, ph[nph - 1].wr, base, tid, TB);
-    chunk_gather<V, R>(lam, lam_st, S, ph[nph - 1].wr, base, tid, TB);
+    chunk_gather<V, R>(psi, psi_st, S->scatter_phys, base, tid, TB);
+    chunk_gather<V, R>(lam, lam_st, S->scatter_phys, base, tid, TB);
     for (int p = nph - 1; p >= 0; --p) {
         const cptr<DevPhase> P = ph + p;
         for (int o = (int)P->op_end - 1; o >= (int)P->op_begin; --o) {
-            const cptr<DevOp> op = ops + o;
+            const OpH op = load_op(ops + o);
             op_inverse<T, R, KMAX>(psi, op, mats, ptab, pbase, base);
-            if (op->type == OP_PROT || op->type == OP_PDIAG) {
+            if (op.type == OP_PROT || op.type == OP_PDIAG) {
                 const double g = op_dgrad<T, R>(psi, lam, op, ptab, pbase, base);
                 double total;
                 if (blockDim.x >= 64) {
@@ -246,7 +248,7 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
                     total = 0.0;
                     for (unsigned t = 0; t < blockDim.x; ++t) total += red[t];
                 }
-                if (tid == 0) part[((size_t)b * nslots + op->slot) * nchunks + chunk] = total;
+                if (tid == 0) part[((size_t)b * nslots + op.slot) * nchunks + chunk] = total;
                 __syncthreads();
             }
             op_inverse<T, R, KMAX>(lam, op, mats, ptab, pbase, base);
@@ -256,8 +258,9 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
             chunk_transpose<V, R>(lam, lds, P->rd, ph[p - 1].wr, tid, TB, true);
         }
     }
-    chunk_scatter<V, R>(psi, psi_st, S, ph[0].rd, base, tid, TB);
-    chunk_scatter<V, R>(lam, lam_st, S, ph[0].rd, base, tid, TB);
+    if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
+    chunk_scatter<V, R>(psi, psi_st, S->gather_phys, base, tid, TB);
+    chunk_scatter<V, R>(lam, lam_st, S->gather_phys, base, tid, TB);
 }
 
 // lambda = h(x) psi for a Z-string observable (batch over blockIdx.y)

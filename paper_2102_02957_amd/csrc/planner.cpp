@@ -756,6 +756,17 @@ static void lower_section(Plan &P, int si) {
         for (uint32_t o = P.dphase[ph].op_begin; o < P.dphase[ph].op_end; ++o)
             if (P.dops[o].type != OP_DENSE) dense_only = false;
     ds.flags = dense_only ? SEC_DENSE_ONLY : 0u;
+    // physical bit of every data position where the chunk is gathered / scattered
+    {
+        const DevPhase &f = P.dphase[ds.phase_begin], &l = P.dphase[ds.phase_end - 1];
+        bool moves = false;
+        for (int p = 0; p < C; ++p) {
+            ds.gather_phys[p] = ds.slot_phys[f.rd[p]];
+            ds.scatter_phys[p] = ds.slot_phys[l.wr[p]];
+            if (p >= R && ds.gather_phys[p] != ds.scatter_phys[p]) moves = true;
+        }
+        if (moves && ds.phase_end - ds.phase_begin == 1) ds.flags |= SEC_SYNC_SCATTER;
+    }
     P.dsec.push_back(ds);
 }
 

@@ -69,9 +69,15 @@ struct DevSection {          // 128 bytes
     uint32_t n_params_used;  // parameterised ops in this section
     uint32_t param_slot;     // first adjoint partial slot of this section
     uint32_t flags;          // SEC_DENSE_ONLY: every op is OP_DENSE
-    uint8_t pad[44];
+    uint8_t gather_phys[16]; // data position -> physical bit at the section start
+    uint8_t scatter_phys[16];// data position -> physical bit at the section end
+    uint8_t pad[12];
 };
 constexpr uint32_t SEC_DENSE_ONLY = 1;
+// single-phase section whose scatter sends amplitudes to other threads: without
+// a transposition in between, a workgroup barrier must separate every wave's
+// gather from any wave's scatter (the update is in place)
+constexpr uint32_t SEC_SYNC_SCATTER = 2;
 static_assert(sizeof(DevSection) == 128, "DevSection layout");
 
 // one parameterised op: which parameter drives it and how

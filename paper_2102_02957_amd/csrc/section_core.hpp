@@ -45,6 +45,47 @@ template <typename V> __device__ __forceinline__ V ldc(cptr<V> p) {
     return r;
 }
 
+// Byte tables in constant memory are read a dword at a time: scalar loads have
+// no byte form, and a byte load would go through the vector memory pipeline
+// (with a wait on every outstanding vector load before the byte is usable).
+struct Bytes16 {
+    uint32_t w[4];
+    __device__ __forceinline__ uint32_t operator[](int i) const {
+        return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu;
+    }
+};
+__device__ __forceinline__ Bytes16 ld16(cptr<uint8_t> p) {  // p 4-byte aligned
+    const cptr<uint32_t> q = (cptr<uint32_t>)p;
+    Bytes16 b;
+    b.w[0] = q[0];
+    b.w[1] = q[1];
+    b.w[2] = q[2];
+    b.w[3] = q[3];
+    return b;
+}
+
+// One in-section op, decoded from its four dwords (scalar registers).
+struct OpH {
+    uint32_t type, k, a[5], rot;
+    int32_t arg, slot;
+};
+__device__ __forceinline__ OpH load_op(cptr<DevOp> op) {
+    const cptr<uint32_t> q = (cptr<uint32_t>)op;
+    const uint32_t w0 = q[0], w1 = q[1];
+    OpH h;
+    h.type = w0 & 0xffu;
+    h.k = (w0 >> 8) & 0xffu;
+    h.a[0] = (w0 >> 16) & 0xffu;
+    h.a[1] = w0 >> 24;
+    h.a[2] = w1 & 0xffu;
+    h.a[3] = (w1 >> 8) & 0xffu;
+    h.a[4] = (w1 >> 16) & 0xffu;
+    h.rot = w1 >> 24;
+    h.arg = (int32_t)q[2];
+    h.slot = (int32_t)q[3];
+    return h;
+}
+
 // component-wise select (a select of whole structs becomes a select of their
 // addresses, which would keep the register array in scratch memory)
 template <typename V> __device__ __forceinline__ V sel(bool c, V a, V b) {
@@ -226,44 +267,55 @@ template <typename V> __device__ __forceinline__ int lds_swizzle(int j) {
 
 // ---- chunk-level steps --------------------------------------------------------
 
-// physical-bit offset of data positions [0, R) -> per-register offsets, plus the
-// thread's own offset from positions [R, R + TB)
+// Gather / scatter of one chunk.  phys[p] = physical bit of data position p:
+// positions [0, R) select the register, [R, R + TB) the thread.
+template <typename V, int R>
+__device__ __forceinline__ uint64_t thread_offset(const Bytes16 &phys, unsigned tid, int TB) {
+    uint64_t toff = 0;
+    static_for<8>([&](auto B) __attribute__((always_inline)) {
+        if (B.value < TB) toff |= (uint64_t)((tid >> B.value) & 1u) << phys[R + B.value];
+    });
+    return toff;
+}
+
 template <typename V, int R>
 __device__ __forceinline__ void chunk_gather(V (&a)[1 << R], const V *__restrict__ st,
-                                             cptr<DevSection> S, cptr<uint8_t> map,
-                                             uint64_t base, unsigned tid, int TB) {
-    uint64_t toff = 0;
-    for (int b = 0; b < TB; ++b) toff |= (uint64_t)((tid >> b) & 1u) << S->slot_phys[map[R + b]];
-    uint64_t rbit[R];
-    static_for<R>([&](auto B) __attribute__((always_inline)) {
-        rbit[B.value] = 1ull << S->slot_phys[map[B.value]];
-    });
+                                             cptr<uint8_t> phys_tab, uint64_t base,
+                                             unsigned tid, int TB) {
+    const Bytes16 phys = ld16(phys_tab);
+    const uint64_t toff = base | thread_offset<V, R>(phys, tid, TB);
     static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
         uint64_t off = toff;
         static_for<R>([&](auto B) __attribute__((always_inline)) {
-            if constexpr (((I.value >> B.value) & 1) != 0) off |= rbit[B.value];
+            if constexpr (((I.value >> B.value) & 1) != 0) off |= 1ull << phys[B.value];
         });
-        a[I.value] = st[base | off];
+        a[I.value] = st[off];
     });
 }
 
 template <typename V, int R>
 __device__ __forceinline__ void chunk_scatter(const V (&a)[1 << R], V *__restrict__ st,
-                                              cptr<DevSection> S, cptr<uint8_t> map,
-                                              uint64_t base, unsigned tid, int TB) {
-    uint64_t toff = 0;
-    for (int b = 0; b < TB; ++b) toff |= (uint64_t)((tid >> b) & 1u) << S->slot_phys[map[R + b]];
-    uint64_t rbit[R];
-    static_for<R>([&](auto B) __attribute__((always_inline)) {
-        rbit[B.value] = 1ull << S->slot_phys[map[B.value]];
-    });
+                                              cptr<uint8_t> phys_tab, uint64_t base,
+                                              unsigned tid, int TB) {
+    const Bytes16 phys = ld16(phys_tab);
+    const uint64_t toff = base | thread_offset<V, R>(phys, tid, TB);
     static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
         uint64_t off = toff;
         static_for<R>([&](auto B) __attribute__((always_inline)) {
-            if constexpr (((I.value >> B.value) & 1) != 0) off |= rbit[B.value];
+            if constexpr (((I.value >> B.value) & 1) != 0) off |= 1ull << phys[B.value];
         });
-        st[base | off] = a[I.value];
+        st[off] = a[I.value];
     });
+}
+
+// Between the gather and the scatter of a section flagged SEC_SYNC_SCATTER:
+// every wave's loads of the chunk complete before any wave stores into it.  A
+// workgroup-scope fence does not wait for outstanding vector loads, so the
+// wait is explicit: s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their
+// maxima, gfx9 encoding).
+__device__ __forceinline__ void gather_scatter_barrier() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_s_barrier();
 }
 
 // Workgroup barrier that orders LDS accesses only: outstanding global loads
@@ -277,14 +329,17 @@ __device__ __forceinline__ void lds_barrier() {
 // LDS transposition from position->slot map `from` to map `to`.  Threads with
 // active == false take part in the barriers only.
 template <typename V, int R>
-__device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uint8_t> from,
-                                                cptr<uint8_t> to, unsigned tid, int TB,
+__device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uint8_t> from_tab,
+                                                cptr<uint8_t> to_tab, unsigned tid, int TB,
                                                 bool active) {
+    const Bytes16 from = ld16(from_tab), to = ld16(to_tab);
     uint32_t tw = 0, tr = 0;
-    for (int b = 0; b < TB; ++b) {
-        tw |= ((tid >> b) & 1u) << from[R + b];
-        tr |= ((tid >> b) & 1u) << to[R + b];
-    }
+    static_for<8>([&](auto B) __attribute__((always_inline)) {
+        if (B.value < TB) {
+            tw |= ((tid >> B.value) & 1u) << from[R + B.value];
+            tr |= ((tid >> B.value) & 1u) << to[R + B.value];
+        }
+    });
     uint32_t bw[R], br[R];
     static_for<R>([&](auto B) __attribute__((always_inline)) {
         bw[B.value] = 1u << from[B.value];
@@ -323,43 +378,43 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
     using V = typename Amp<T>::V;
     constexpr int RA = 1 << R;
     for (uint32_t o = o_begin; o < o_end; ++o) {
-        const cptr<DevOp> op = ops + o;
-        const uint32_t type = op->type;
-        const uint32_t k = op->k;
+        const OpH op = load_op(ops + o);
+        const uint32_t type = op.type;
+        const uint32_t k = op.k;
         if (type == OP_DENSE) {
-            const cptr<V> mm = mats + op->arg;
-            if (k == 1) dispatch1<V, R>(a, op->a[0], mm);
-            else if (k == 2) dispatch2<V, R>(a, op->a[0], op->a[1], mm);
+            const cptr<V> mm = mats + op.arg;
+            if (k == 1) dispatch1<V, R>(a, op.a[0], mm);
+            else if (k == 2) dispatch2<V, R>(a, op.a[0], op.a[1], mm);
             else if constexpr (KMAX >= 3) {
-                if (k == 3) dispatch3<V, R>(a, op->a[0], op->a[1], op->a[2], mm);
+                if (k == 3) dispatch3<V, R>(a, op.a[0], op.a[1], op.a[2], mm);
                 else if constexpr (KMAX >= 4) {
-                    if (k == 4) dispatch4<V, R>(a, op->a[0], op->a[1], op->a[2], op->a[3], mm);
+                    if (k == 4) dispatch4<V, R>(a, op.a[0], op.a[1], op.a[2], op.a[3], mm);
                     else if constexpr (KMAX >= 5) {
-                        if (op->a[0] == 0 && op->a[4] == 4) dense_apply<V, R, 0, 1, 2, 3, 4>(a, mm);
+                        if (op.a[0] == 0 && op.a[4] == 4) dense_apply<V, R, 0, 1, 2, 3, 4>(a, mm);
                     }
                 }
             }
         } else if constexpr (DENSE_ONLY) {
             // sections flagged dense-only carry no other op
         } else if (type == OP_XREG) {
-            dispatch_cx<V, R>(a, op->a[0], false, 0, pbase, 0);
+            dispatch_cx<V, R>(a, op.a[0], false, 0, pbase, 0);
         } else if (type == OP_CX) {
-            const unsigned s = op->a[1];
+            const unsigned s = op.a[1];
             const unsigned gbit =
                 s >= SRC_GLOBAL ? (unsigned)((base >> (s - SRC_GLOBAL)) & 1ull) : 0u;
-            dispatch_cx<V, R>(a, op->a[0], true, s, pbase, gbit);
+            dispatch_cx<V, R>(a, op.a[0], true, s, pbase, gbit);
         } else if (type == OP_DIAG) {
-            const cptr<V> tab = mats + op->arg;
+            const cptr<V> tab = mats + op.arg;
             if (k == 1) {
                 const V d0 = ldc(tab), d1 = ldc(tab + 1);
-                const unsigned s0 = op->a[0];
+                const unsigned s0 = op.a[0];
                 static_for<RA>([&](auto I) __attribute__((always_inline)) {
                     const unsigned b0 = src_bit(s0, pbase | I.value, base);
                     a[I.value] = cmul(sel(b0 != 0, d1, d0), a[I.value]);
                 });
             } else if (k == 2) {
                 const V d0 = ldc(tab), d1 = ldc(tab + 1), d2 = ldc(tab + 2), d3 = ldc(tab + 3);
-                const unsigned s0 = op->a[0], s1 = op->a[1];
+                const unsigned s0 = op.a[0], s1 = op.a[1];
                 static_for<RA>([&](auto I) __attribute__((always_inline)) {
                     const unsigned b0 = src_bit(s0, pbase | I.value, base);
                     const unsigned b1 = src_bit(s1, pbase | I.value, base);
@@ -369,26 +424,27 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
             } else {
                 static_for<RA>([&](auto I) __attribute__((always_inline)) {
                     unsigned idx = 0;
-                    for (uint32_t j = 0; j < k; ++j)
-                        idx |= src_bit(op->a[j], pbase | I.value, base) << j;
+                    static_for<5>([&](auto J) __attribute__((always_inline)) {
+                        if (J.value < k) idx |= src_bit(op.a[J.value], pbase | I.value, base) << J.value;
+                    });
                     a[I.value] = cmul(ldc(tab + idx), a[I.value]);
                 });
             }
         } else if (type == OP_PROT) {
-            const V cs = ldc(ptab + 2 * op->slot), sn = ldc(ptab + 2 * op->slot + 1);
+            const V cs = ldc(ptab + 2 * op.slot), sn = ldc(ptab + 2 * op.slot + 1);
             V ms;
-            if (op->rot == ROT_RY) {
+            if (op.rot == ROT_RY) {
                 ms.x = -sn.x;
                 ms.y = 0;
-                dispatch1_val<V, R>(a, op->a[0], cs, ms, sn, cs);
+                dispatch1_val<V, R>(a, op.a[0], cs, ms, sn, cs);
             } else {  // RX: [[c, -i s], [-i s, c]]
                 ms.x = 0;
                 ms.y = -sn.x;
-                dispatch1_val<V, R>(a, op->a[0], cs, ms, ms, cs);
+                dispatch1_val<V, R>(a, op.a[0], cs, ms, ms, cs);
             }
         } else if (type == OP_PDIAG) {
-            const V d0 = ldc(ptab + 2 * op->slot), d1 = ldc(ptab + 2 * op->slot + 1);
-            const unsigned s0 = op->a[0];
+            const V d0 = ldc(ptab + 2 * op.slot), d1 = ldc(ptab + 2 * op.slot + 1);
+            const unsigned s0 = op.a[0];
             static_for<RA>([&](auto I) __attribute__((always_inline)) {
                 a[I.value] = cmul(sel(src_bit(s0, pbase | I.value, base) != 0, d1, d0), a[I.value]);
             });
@@ -396,10 +452,21 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
     }
 }
 
+// Physical index of the chunk's first amplitude: the bits of the chunk id
+// deposited into the non-local bits, i.e. a zero inserted at every local bit
+// (slot_phys is ascending).
 __device__ __forceinline__ uint64_t chunk_base(cptr<DevSection> S, uint64_t chunk) {
-    uint64_t base = 0;
-    for (uint32_t k = 0; k < S->n_nl; ++k) base |= ((chunk >> k) & 1ull) << S->nl_phys[k];
-    return base;
+    const Bytes16 loc = ld16(S->slot_phys);
+    const uint32_t c = S->c;
+    uint64_t x = chunk;
+    static_for<16>([&](auto I) __attribute__((always_inline)) {
+        if (I.value < c) {
+            const uint32_t l = loc[I.value];
+            const uint64_t low = x & ((1ull << l) - 1ull);
+            x = ((x >> l) << (l + 1)) | low;
+        }
+    });
+    return x;
 }
 
 // All phases of one section on the registers of one chunk (no HBM traffic).
@@ -434,9 +501,10 @@ __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
     const cptr<DevPhase> ph = phases + S->phase_begin;
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
-    if (active) chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
+    if (active) chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
     chunk_phases<T, R, KMAX, DENSE_ONLY>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
-    if (active) chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
+    if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
+    if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
 }
 
 // sum over the thread's registers of |a|^2 in FP64
@@ -464,9 +532,10 @@ __device__ __forceinline__ double run_chunk_norm(typename Amp<T>::V *__restrict_
     const cptr<DevPhase> ph = phases + S->phase_begin;
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
-    if (active) chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
+    if (active) chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
     chunk_phases<T, R, KMAX>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
-    if (active) chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
+    if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
+    if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
     red[tid] = active ? reg_norm2<V, R>(a) : 0.0;
     __syncthreads();
     for (unsigned s = blockDim.x / 2; s > 0; s >>= 1) {

@@ -78,17 +78,18 @@ k_section_pipe(typename Amp<T>::V *__restrict__ state, int n,
 
     V a[1 << R], nx[1 << R];
     uint64_t base = chunk_base(S, g);
-    chunk_gather<V, R>(a, st, S, ph[0].rd, base, tid, TB);
+    chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
     for (;;) {
         const uint64_t gn = g + stride;
         const bool more = gn < g_end;
         uint64_t base_n = 0;
         if (more) {
             base_n = chunk_base(S, gn);
-            chunk_gather<V, R>(nx, st, S, ph[0].rd, base_n, tid, TB);
+            chunk_gather<V, R>(nx, st, S->gather_phys, base_n, tid, TB);
         }
         chunk_phases<T, R, KMAX, DENSE_ONLY>(a, ph, nph, ops, mats, ptab, base, lds, TB, true);
-        chunk_scatter<V, R>(a, st, S, ph[nph - 1].wr, base, tid, TB);
+        if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
+        chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
         if (!more) break;
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) { a[I.value] = nx[I.value]; });
         base = base_n;

@@ -145,6 +145,26 @@ def test_permutation_circuits_bit_exact(torch, ctxs, dt, mode, swap_mode):
 
 
 @pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_swap_only_sections_in_place(torch, ctxs, dt):
+    """SWAP-only sections: one phase, no transposition, amplitudes change
+    thread (and wave) between the gather and the in-place scatter.  Bit-exact,
+    on every one of several runs, with thousands of workgroups in flight."""
+    n = 21
+    gates = W.random_circuit(n, 40, 5, kinds=["swap"])
+    psi0 = random_state(n, 7)
+    if dt == B.QSV_C64:
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    want = oracle.apply_circuit(n, gates, psi0)
+    if dt == B.QSV_C64:
+        want = want.astype(np.complex64)
+    for _ in range(3):
+        got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=12)
+        if dt == B.QSV_C64:
+            got = got.astype(np.complex64)
+        assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
 def test_materialised_swaps(torch, ctxs, dt):
     n = 16
     gates = W.quantum_volume(n, 8, 5)
