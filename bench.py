@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--pinned", type=int, default=None)
     ap.add_argument("--fusion", type=int, default=None)
     ap.add_argument("--register-bits", type=int, default=None)
+    ap.add_argument("--io-phases", type=int, default=None)
     return ap.parse_args()
 
 
@@ -114,7 +115,8 @@ def main():
     gates = W.quantum_volume(n, n, args.seed)
     t0 = time.perf_counter()
     plan = B.Plan(n, gates, dt, chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
-                  fusion_max_qubits=args.fusion, register_bits=args.register_bits)
+                  fusion_max_qubits=args.fusion, register_bits=args.register_bits,
+                  io_phases=args.io_phases)
     t_plan = time.perf_counter() - t0
     st = plan.stats()
     S = st["n_sections"]

@@ -95,6 +95,11 @@ typedef struct {
     int32_t diag_free;           /* 1: diagonal gates and CX controls need not be local (Sec. V-A:
                                     QFT's diagonal gates need less exchange) */
     int32_t register_bits;       /* r: amplitudes per GPU thread = 2^r; 0 = default */
+    int32_t io_phases;           /* 1: a section whose first (last) phase holds one of the six
+                                    lowest local bits in registers gathers (scatters) through an
+                                    extra op-free phase in which lanes sit on those bits: one more
+                                    LDS transposition for coalesced HBM access (large states
+                                    only); 0: gather and scatter in the phases' own maps */
 } qsv_options;
 
 /* Fill *opt with the defaults for dt. */

@@ -42,7 +42,8 @@ class Gate(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("chunk_bits", ctypes.c_int32), ("pinned_low_bits", ctypes.c_int32),
                 ("fusion_max_qubits", ctypes.c_int32), ("swap_mode", ctypes.c_int32),
-                ("diag_free", ctypes.c_int32), ("register_bits", ctypes.c_int32)]
+                ("diag_free", ctypes.c_int32), ("register_bits", ctypes.c_int32),
+                ("io_phases", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):

@@ -40,6 +40,7 @@ void default_options(qsv_dtype dt, qsv_options &o) {
     o.swap_mode = QSV_SWAP_REMAP;
     o.diag_free = 1;
     o.register_bits = dt == QSV_C64 ? 5 : 4;
+    o.io_phases = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -751,6 +752,37 @@ static void lower_section(Plan &P, int si) {
         P.dphase.push_back(cur);
     }
     ds.phase_end = (uint32_t)P.dphase.size();
+    // HBM access through the coalesced map: lanes on the lowest local bits, then
+    // the registers, then the remaining thread bits.  When the first (last)
+    // phase puts a low bit in registers, an op-free phase in that map goes in
+    // front (behind): one more LDS transposition instead of scattered 16-byte
+    // accesses.  Only for states of many chunks (small ones stay in cache).
+    if (P.opt.io_phases && C > R && n - C >= 8) {
+        const int nlane = std::min(6, C - R);
+        DevPhase io;
+        std::memset(&io, 0, sizeof(io));
+        for (int p = 0; p < C; ++p) {
+            int sl;
+            if (p < R) sl = nlane + p;
+            else if (p - R < nlane) sl = p - R;
+            else sl = p;
+            io.rd[p] = io.wr[p] = (uint8_t)sl;
+        }
+        auto coalesced = [&](const uint8_t *m) {
+            for (int b = 0; b < nlane; ++b)
+                if (m[R + b] != b) return false;
+            return true;
+        };
+        if (!coalesced(P.dphase[ds.phase_begin].rd)) {
+            io.op_begin = io.op_end = P.dphase[ds.phase_begin].op_begin;
+            P.dphase.insert(P.dphase.begin() + ds.phase_begin, io);
+        }
+        if (!coalesced(P.dphase.back().wr)) {
+            io.op_begin = io.op_end = P.dphase.back().op_end;
+            P.dphase.push_back(io);
+        }
+        ds.phase_end = (uint32_t)P.dphase.size();
+    }
     bool dense_only = true;
     for (uint32_t ph = ds.phase_begin; ph < ds.phase_end; ++ph)
         for (uint32_t o = P.dphase[ph].op_begin; o < P.dphase[ph].op_end; ++o)
@@ -847,6 +879,10 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     }
     if (o.register_bits < 1 || o.register_bits > 5) {
         err = "register_bits must be in [1, 5]";
+        return QSV_E_INVALID;
+    }
+    if (o.io_phases != 0 && o.io_phases != 1) {
+        err = "io_phases must be 0 or 1";
         return QSV_E_INVALID;
     }
     if (o.swap_mode != QSV_SWAP_REMAP && o.swap_mode != QSV_SWAP_MATERIALIZE) {

@@ -258,10 +258,13 @@ __device__ __forceinline__ unsigned src_bit(unsigned s, uint32_t pidx, uint64_t 
     return s >= SRC_GLOBAL ? (unsigned)((base >> (s - SRC_GLOBAL)) & 1ull) : ((pidx >> s) & 1u);
 }
 
-template <typename V> __device__ __forceinline__ int lds_swizzle(int j) {
-    // XOR-fold the higher index bits into the bank-selecting low bits (128 B rows)
-    if constexpr (sizeof(V) == 16) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7);
-    else return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15);
+// LDS bank swizzle: XOR-fold the higher index bits into the bank-selecting low
+// bits (128 B rows).  The map is linear over GF(2), swz(x ^ y) = swz(x) ^ swz(y),
+// so the address of every element is the thread's swizzled part XOR a uniform
+// (scalar) swizzled register part.
+template <typename V> __device__ __forceinline__ uint32_t lds_swizzle(uint32_t j) {
+    if constexpr (sizeof(V) == 16) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7u);
+    else return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15u);
 }
 
 
@@ -283,13 +286,13 @@ __device__ __forceinline__ void chunk_gather(V (&a)[1 << R], const V *__restrict
                                              cptr<uint8_t> phys_tab, uint64_t base,
                                              unsigned tid, int TB) {
     const Bytes16 phys = ld16(phys_tab);
-    const uint64_t toff = base | thread_offset<V, R>(phys, tid, TB);
+    const V *tp = st + (base | thread_offset<V, R>(phys, tid, TB));
     static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
-        uint64_t off = toff;
+        uint64_t ro = 0;  // uniform
         static_for<R>([&](auto B) __attribute__((always_inline)) {
-            if constexpr (((I.value >> B.value) & 1) != 0) off |= 1ull << phys[B.value];
+            if constexpr (((I.value >> B.value) & 1) != 0) ro |= 1ull << phys[B.value];
         });
-        a[I.value] = st[off];
+        a[I.value] = tp[ro];
     });
 }
 
@@ -298,13 +301,13 @@ __device__ __forceinline__ void chunk_scatter(const V (&a)[1 << R], V *__restric
                                               cptr<uint8_t> phys_tab, uint64_t base,
                                               unsigned tid, int TB) {
     const Bytes16 phys = ld16(phys_tab);
-    const uint64_t toff = base | thread_offset<V, R>(phys, tid, TB);
+    V *tp = st + (base | thread_offset<V, R>(phys, tid, TB));
     static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
-        uint64_t off = toff;
+        uint64_t ro = 0;  // uniform
         static_for<R>([&](auto B) __attribute__((always_inline)) {
-            if constexpr (((I.value >> B.value) & 1) != 0) off |= 1ull << phys[B.value];
+            if constexpr (((I.value >> B.value) & 1) != 0) ro |= 1ull << phys[B.value];
         });
-        st[off] = a[I.value];
+        tp[ro] = a[I.value];
     });
 }
 
@@ -340,29 +343,30 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
             tr |= ((tid >> B.value) & 1u) << to[R + B.value];
         }
     });
-    uint32_t bw[R], br[R];
-    static_for<R>([&](auto B) __attribute__((always_inline)) {
-        bw[B.value] = 1u << from[B.value];
-        br[B.value] = 1u << to[B.value];
-    });
+    // byte offsets: thread part (per lane) ^ register part (uniform)
+    char *lb = reinterpret_cast<char *>(lds);
+    const uint32_t tws = lds_swizzle<V>(tw) * (uint32_t)sizeof(V);
+    const uint32_t trs = lds_swizzle<V>(tr) * (uint32_t)sizeof(V);
     lds_barrier();
     if (active) {
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
-            uint32_t j = tw;
+            uint32_t u = 0;
             static_for<R>([&](auto B) __attribute__((always_inline)) {
-                if constexpr (((I.value >> B.value) & 1) != 0) j |= bw[B.value];
+                if constexpr (((I.value >> B.value) & 1) != 0)
+                    u ^= lds_swizzle<V>(1u << from[B.value]) * (uint32_t)sizeof(V);
             });
-            lds[lds_swizzle<V>((int)j)] = a[I.value];
+            *reinterpret_cast<V *>(lb + (tws ^ u)) = a[I.value];
         });
     }
     lds_barrier();
     if (active) {
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
-            uint32_t j = tr;
+            uint32_t u = 0;
             static_for<R>([&](auto B) __attribute__((always_inline)) {
-                if constexpr (((I.value >> B.value) & 1) != 0) j |= br[B.value];
+                if constexpr (((I.value >> B.value) & 1) != 0)
+                    u ^= lds_swizzle<V>(1u << to[B.value]) * (uint32_t)sizeof(V);
             });
-            a[I.value] = lds[lds_swizzle<V>((int)j)];
+            a[I.value] = *reinterpret_cast<const V *>(lb + (trs ^ u));
         });
     }
 }

@@ -79,6 +79,10 @@ k_section_pipe(typename Amp<T>::V *__restrict__ state, int n,
     V a[1 << R], nx[1 << R];
     uint64_t base = chunk_base(S, g);
     chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
+    // Complete the first gather here: the wait-count bookkeeping merges the loop
+    // entry with the back edge, and loads still pending on a[] at entry would
+    // make every iteration wait for its own prefetch before the first LDS write.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     for (;;) {
         const uint64_t gn = g + stride;
         const bool more = gn < g_end;
