@@ -94,7 +94,8 @@ typedef struct {
                                     amplitudes, Sec. IV-C Fig. "chunk_swap") */
     int32_t diag_free;           /* 1: diagonal gates and CX controls need not be local (Sec. V-A:
                                     QFT's diagonal gates need less exchange) */
-    int32_t register_bits;       /* r: amplitudes per GPU thread = 2^r; 0 = default */
+    int32_t register_bits;       /* r: amplitudes per GPU thread = 2^r; 0 = default.  A chunk
+                                    runs on 2^(c-r) threads: c - r <= 9 for r <= 4, <= 8 for r = 5 */
     int32_t io_phases;           /* 1: a section whose first (last) phase holds one of the six
                                     lowest local bits in registers gathers (scatters) through an
                                     extra op-free phase in which lanes sit on those bits: one more

@@ -912,8 +912,9 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         err = "a gate acts on more qubits than the chunk holds";
         return QSV_E_INVALID;
     }
-    if (P.c - P.r > 8) {
-        err = "chunk_bits - register_bits must be <= 8 (256 threads per workgroup)";
+    if (P.c - P.r > (P.r <= 4 ? 9 : 8)) {
+        err = "chunk_bits - register_bits must be <= 9 for register_bits <= 4 and <= 8 for "
+              "register_bits = 5 (512 / 256 threads per workgroup)";
         return QSV_E_INVALID;
     }
     int maxlocal = 1;

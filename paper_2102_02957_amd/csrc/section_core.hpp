@@ -275,7 +275,7 @@ template <typename V> __device__ __forceinline__ uint32_t lds_swizzle(uint32_t j
 template <typename V, int R>
 __device__ __forceinline__ uint64_t thread_offset(const Bytes16 &phys, unsigned tid, int TB) {
     uint64_t toff = 0;
-    static_for<8>([&](auto B) __attribute__((always_inline)) {
+    static_for<9>([&](auto B) __attribute__((always_inline)) {
         if (B.value < TB) toff |= (uint64_t)((tid >> B.value) & 1u) << phys[R + B.value];
     });
     return toff;
@@ -337,7 +337,7 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
                                                 bool active) {
     const Bytes16 from = ld16(from_tab), to = ld16(to_tab);
     uint32_t tw = 0, tr = 0;
-    static_for<8>([&](auto B) __attribute__((always_inline)) {
+    static_for<9>([&](auto B) __attribute__((always_inline)) {
         if (B.value < TB) {
             tw |= ((tid >> B.value) & 1u) << from[R + B.value];
             tr |= ((tid >> B.value) & 1u) << to[R + B.value];

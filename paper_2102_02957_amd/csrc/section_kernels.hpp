@@ -28,8 +28,12 @@ using namespace sec;
 
 // KMAX: widest dense op the kernel instance carries code for (register pressure
 // of the whole kernel follows the widest case, so narrow plans use KMAX = 2).
+// Up to 512 threads per workgroup for R <= 4 (chunk_bits - R <= 9), 256 for R = 5
+// (whose amplitude registers need the larger per-thread register budget).
+template <int R> constexpr int section_max_threads() { return R <= 4 ? 512 : 256; }
+
 template <typename T, int R, int KMAX, bool DENSE_ONLY>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(section_max_threads<R>())
 k_section(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__restrict__ secs_g,
           int sec, const DevPhase *__restrict__ phases_g, const DevOp *__restrict__ ops_g,
           const typename Amp<T>::V *__restrict__ mats_g, const typename Amp<T>::V *__restrict__ ptab_g,
@@ -119,7 +123,7 @@ inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv
         }
         attr_set = true;
     }
-    if (c - R > 8 || c < R) return hipErrorInvalidConfiguration;
+    if ((1 << (c - R)) > section_max_threads<R>() || c < R) return hipErrorInvalidConfiguration;
     const uint64_t nchunks = 1ull << (n - c);
     dim3 block(1u << (c - R));
     // persistent pipelined kernel when every resident workgroup gets >= 2 chunks
@@ -147,7 +151,7 @@ inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv
         return e && e[0] == '1';
     }();
     if constexpr (R >= 4 && KMAX == 2) {
-      if (pipe_on && batch == 1 && G >= 8 && nchunks >= 2 * G && nchunks % 8 == 0) {
+      if (pipe_on && batch == 1 && c - R <= 8 && G >= 8 && nchunks >= 2 * G && nchunks % 8 == 0) {
         hipLaunchKernelGGL((k_section_pipe<T, R, KMAX, DENSE_ONLY>), dim3((unsigned)G, 1), block, lds_bytes, s,
                            (V *)state, n, pv.secs, sec, pv.phases, pv.ops, (const V *)pv.mats,
                            (const V *)ptab, nslots, nchunks);

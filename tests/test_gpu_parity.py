@@ -90,6 +90,7 @@ RANDOM_CASES = [
     (16, 12, 4, 3, 2, 9),
     (17, 11, 5, 4, 3, 10),
     (18, 13, 5, 4, 4, 11),
+    (19, 13, 4, 3, 2, 12),   # 2^9 threads per workgroup
 ]
 
 
@@ -142,6 +143,16 @@ def test_permutation_circuits_bit_exact(torch, ctxs, dt, mode, swap_mode):
         want = want.astype(np.complex64)
         got = got.astype(np.complex64)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_qv_512_thread_sections(torch, ctxs, dt):
+    """chunk_bits 13 with 16 amplitudes per thread: 512-thread workgroups."""
+    n = 21
+    gates = W.quantum_volume(n, 8, 6)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, chunk_bits=13, register_bits=4)
+    assert plan.stats()["n_sections"] > 1
+    assert_close(got, oracle.apply_circuit(n, gates), dt, "qv21 c13 r4")
 
 
 @pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])

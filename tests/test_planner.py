@@ -162,7 +162,7 @@ def test_invalid_options_rejected():
         B.Plan(20, W.ghz(20), 3)
     with pytest.raises(B.QsvError) as e:
         B.Plan(20, W.ghz(20), B.QSV_C128, chunk_bits=13, register_bits=3)
-    assert "256 threads" in str(e.value)
+    assert "threads per workgroup" in str(e.value)
 
 
 def test_empty_circuit():
