@@ -177,6 +177,29 @@ std::vector<int> scan_rest(const Blocker &B, const std::vector<int> &rem, uint64
     return next;
 }
 
+// Sections a greedy plan (best-count candidate per section, no lookahead)
+// needs for the gates in `rem` (remap semantics).
+int rollout_sections(const Blocker &B, std::vector<int> rem, uint64_t start, int c, int n) {
+    int sections = 0;
+    std::vector<uint64_t> cands;
+    while (!rem.empty()) {
+        chunk_candidates(B, rem, start, c, n, cands);
+        uint64_t best = 0;
+        int best_cnt = -1;
+        for (uint64_t cand : cands) {
+            const uint64_t full = fill_low(cand, c, n);
+            const int cnt = scan_count(B, rem, full);
+            if (cnt > best_cnt) {
+                best_cnt = cnt;
+                best = full;
+            }
+        }
+        rem = scan_rest(B, rem, best);
+        ++sections;
+    }
+    return sections;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -303,6 +326,11 @@ static void block_circuit(Plan &P) {
     for (int q = 0; q < n; ++q) layout[q] = inv[q] = q;
     const uint64_t pinned = (L > 0) ? ((1ull << L) - 1) : 0;
 
+    // Candidate scoring: for circuits of up to 1024 gates (remap mode) each
+    // candidate is scored by the sections a greedy plan of the rest needs
+    // (about a second of host time at 600 gates); larger circuits use one
+    // section of lookahead.
+    const bool rollout = !materialise && P.gates.size() <= 1024;
     P.sections.clear();
     P.chunk_swaps = 0;
     uint64_t prev_local_logical = 0;
@@ -315,7 +343,7 @@ static void block_circuit(Plan &P) {
         std::vector<uint64_t> cands, cands2;
         chunk_candidates(B, rem, start, c, n, cands);
         uint64_t best = 0;
-        int best_score = -1, best_cnt = -1;
+        int best_score = INT32_MIN, best_cnt = -1;
         for (uint64_t cand : cands) {
             uint64_t full = cand;
             if (materialise) {
@@ -324,15 +352,21 @@ static void block_circuit(Plan &P) {
             }
             full = fill_low(full, c, n);
             int cnt = scan_count(B, rem, full);
-            // one section of lookahead: gates this section plus the best next one
-            int score = cnt;
             std::vector<int> nxt = scan_rest(B, rem, full);
-            if (!nxt.empty()) {
-                chunk_candidates(B, nxt, start, c, n, cands2);
-                int b2 = 0;
-                for (uint64_t c2 : cands2)
-                    b2 = std::max(b2, scan_count(B, nxt, fill_low(c2, c, n)));
-                score += b2;
+            int score;
+            if (rollout) {
+                // fewest sections for the rest of the circuit under the greedy rule
+                score = -rollout_sections(B, nxt, start, c, n);
+            } else {
+                // one section of lookahead: gates this section plus the best next one
+                score = cnt;
+                if (!nxt.empty()) {
+                    chunk_candidates(B, nxt, start, c, n, cands2);
+                    int b2 = 0;
+                    for (uint64_t c2 : cands2)
+                        b2 = std::max(b2, scan_count(B, nxt, fill_low(c2, c, n)));
+                    score += b2;
+                }
             }
             if (score > best_score || (score == best_score && cnt > best_cnt)) {
                 best_score = score;
