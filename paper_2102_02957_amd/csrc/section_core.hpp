@@ -69,6 +69,33 @@ struct OpH {
     uint32_t type, k, a[5], rot;
     int32_t arg, slot;
 };
+struct OpRaw {
+    uint32_t w[4];
+};
+__device__ __forceinline__ OpRaw load_op_raw(cptr<DevOp> op) {
+    const cptr<uint32_t> q = (cptr<uint32_t>)op;
+    OpRaw r;
+    r.w[0] = q[0];
+    r.w[1] = q[1];
+    r.w[2] = q[2];
+    r.w[3] = q[3];
+    return r;
+}
+__device__ __forceinline__ OpH decode_op(const OpRaw &r) {
+    const uint32_t w0 = r.w[0], w1 = r.w[1];
+    OpH h;
+    h.type = w0 & 0xffu;
+    h.k = (w0 >> 8) & 0xffu;
+    h.a[0] = (w0 >> 16) & 0xffu;
+    h.a[1] = w0 >> 24;
+    h.a[2] = w1 & 0xffu;
+    h.a[3] = (w1 >> 8) & 0xffu;
+    h.a[4] = (w1 >> 16) & 0xffu;
+    h.rot = w1 >> 24;
+    h.arg = (int32_t)r.w[2];
+    h.slot = (int32_t)r.w[3];
+    return h;
+}
 __device__ __forceinline__ OpH load_op(cptr<DevOp> op) {
     const cptr<uint32_t> q = (cptr<uint32_t>)op;
     const uint32_t w0 = q[0], w1 = q[1];
@@ -381,8 +408,13 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
                                           uint64_t base) {
     using V = typename Amp<T>::V;
     constexpr int RA = 1 << R;
+    if (o_begin >= o_end) return;
+    // the next op's record is loaded while the current op computes (decoded
+    // only when its op starts), so every op's matrix loads issue at once
+    OpRaw nxt = load_op_raw(ops + o_begin);
     for (uint32_t o = o_begin; o < o_end; ++o) {
-        const OpH op = load_op(ops + o);
+        const OpH op = decode_op(nxt);
+        if (o + 1 < o_end) nxt = load_op_raw(ops + o + 1);
         const uint32_t type = op.type;
         const uint32_t k = op.k;
         if (type == OP_DENSE) {
