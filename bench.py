@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--fusion", type=int, default=None)
     ap.add_argument("--register-bits", type=int, default=None)
     ap.add_argument("--io-phases", type=int, default=None)
+    ap.add_argument("--workload", choices=["qv", "trajectories", "adjoint"], default="qv",
+                    help="qv: the headline blocked apply (default); trajectories: 512 noisy "
+                         "trajectories in one graph launch; adjoint: 20-qubit ansatz gradients")
     return ap.parse_args()
 
 
@@ -59,6 +62,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        return 1
+
+
 def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
     """The oracle as it stands, on a bounded sample of the same workload:
     a 24-qubit Quantum-Volume circuit, gates applied until ~15 s have passed;
@@ -66,11 +77,7 @@ def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
     import numpy as np
     import oracle
     from paper_2102_02957_amd import workloads as W
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = 1
+    threads = blas_threads()
     ns = 24
     gates = W.quantum_volume(ns, ns, seed)
     psi = oracle.zero_state(ns)
@@ -98,6 +105,146 @@ def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
     }
 
 
+def timed_calls(torch, fn, steps, warmup):
+    """Run fn warmup + steps times on the current stream; return the wall time
+    of the timed calls (seconds) and the event time on the current stream (ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, e0.elapsed_time(e1)
+
+
+def bench_trajectories(args, torch, B, W):
+    """512 Pauli-noise trajectories (10-20 qubits, depth 40, p = 1e-3),
+    complex64 with FP64 renormalisation: one captured graph per call."""
+    trajs = W.noisy_trajectories(512, 10, 20, 40, 1e-3, args.seed)
+    t0 = time.perf_counter()
+    plans = [B.Plan(n, g, B.QSV_C64) for n, g in trajs]
+    t_plan = time.perf_counter() - t0
+    offs, o = [], 0
+    for n, _ in trajs:
+        offs.append(o)
+        o += 1 << n
+    ctx = B.Context(B.QSV_C64)
+    states = torch.empty(o, dtype=torch.complex64, device="cuda")
+    norms = torch.empty(len(trajs), dtype=torch.float64, device="cuda")
+    step_bytes = sum(p.stats()["n_sections"] * 2.0 * (1 << p.n) * 8 for p in plans)
+    gates = sum(len(g) for _, g in trajs)
+    wall, ev_ms = timed_calls(torch, lambda: ctx.batch_run(plans, offs, states, norms),
+                              args.steps, max(1, args.warmup))
+    nh = norms.cpu().numpy()
+    log("trajectories: %.3f ms per launch, norms in [%.6f, %.6f]" % (ev_ms / args.steps, nh.min(), nh.max()))
+    ms = wall * 1e3 / args.steps
+    rec = {
+        "metric": "noisy trajectories per second (512 states, 10-20 qubits, one graph launch)",
+        "value": round(len(trajs) * args.steps / wall, 1), "unit": "trajectories/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512 trajectories, n ~ U{10..20}, depth 40 U3+CX, Pauli p=1e-3, "
+                               "complex64, seed %d" % args.seed,
+                   "gates": gates, "states_mib": round(o * 8 / 2 ** 20, 1), "plan_s": round(t_plan, 3)},
+        "gates_per_s": round(gates * args.steps / wall, 1),
+        "roofline": {"bound": "hbm", "kernel": "batch graph (k_batch_init, k_batch, k_batch_scale)",
+                     "achieved": round(step_bytes / (ev_ms / args.steps * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(step_bytes / (ev_ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "note": "algorithmic bytes = sum over trajectories of sections x 2 x 2^n x 8 B; "
+                             "states of 10-20 qubits are largely cache-resident"},
+    }
+    if not args.skip_cpu:
+        import oracle
+        sample = sorted(range(len(trajs)), key=lambda b: trajs[b][0])
+        t0 = time.perf_counter()
+        work_done, k = 0.0, 0
+        while k < len(sample) and time.perf_counter() - t0 < 10.0:
+            n, g = trajs[sample[k]]
+            oracle.apply_circuit(n, g)
+            work_done += len(g) * float(1 << n)
+            k += 1
+        dt_cpu = time.perf_counter() - t0
+        work_all = sum(len(g) * float(1 << n) for n, g in trajs)
+        t_full = dt_cpu * work_all / work_done
+        rec["cpu_baseline"] = {"value": round(len(trajs) / t_full, 3), "unit": "trajectories/s",
+                               "cores": blas_threads(), "kind": "oracle",
+                               "sample": "%d smallest trajectories in %.1f s, scaled by gates x amplitudes "
+                                         "to all 512 (extrapolated %.0f s)" % (k, dt_cpu, t_full)}
+    print(json.dumps(rec), flush=True)
+
+
+def bench_adjoint(args, torch, B, W):
+    """Adjoint gradient: 20-qubit hardware-efficient ansatz, 40 layers of RY.RZ
+    + CX ring (1600 parameters), batch 64, H = sum Z_i Z_{i+1} (periodic)."""
+    n, layers, batch = 20, 40, 64
+    dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64
+    tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
+    es = 16 if dt == B.QSV_C128 else 8
+    tmpl = W.hardware_efficient_ansatz(n, layers)
+    theta = torch.from_numpy(W.ansatz_parameters(n, layers, batch, args.seed)).cuda()
+    terms = [(1.0, (1 << i) | (1 << ((i + 1) % n))) for i in range(n)]
+    t0 = time.perf_counter()
+    plan = B.Plan(n, tmpl, dt, fusion_max_qubits=2)
+    t_plan = time.perf_counter() - t0
+    S = plan.stats()["n_sections"]
+    ctx = B.Context(dt)
+    psi = torch.empty(batch << n, dtype=tdt, device="cuda")
+    lam = torch.empty_like(psi)
+    energy = torch.empty(batch, dtype=torch.float64, device="cuda")
+    grad = torch.empty(batch, 2 * n * layers, dtype=torch.float64, device="cuda")
+    call = lambda: ctx.adjoint_grad(plan, terms, theta, psi, lam, energy, grad)
+    wall, ev_ms = timed_calls(torch, call, args.steps, max(1, args.warmup))
+    # forward sections (read + write psi), H psi (read psi, write lambda), energy
+    # (read psi), reverse sections (read + write psi and lambda)
+    call_bytes = batch * (6.0 * S + 3.0) * (1 << n) * es
+    ms = wall * 1e3 / args.steps
+    log("adjoint: %.3f ms per call, E[0] = %.6f" % (ev_ms / args.steps, energy[0].item()))
+    rec = {
+        "metric": "adjoint gradients per second (20-qubit ansatz, 1600 parameters)",
+        "value": round(batch * args.steps / wall, 2), "unit": "gradients/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if dt == B.QSV_C128 else "f32", "data": "synthetic",
+        "config": {"workload": "hardware-efficient ansatz 20q x 40 layers (RY.RZ + CX ring), "
+                               "batch %d, H = sum Z_i Z_i+1, %s, seed %d" % (batch, args.dtype, args.seed),
+                   "sections": S, "plan_s": round(t_plan, 3)},
+        "roofline": {"bound": "hbm", "kernel": "qsv_adjoint_grad (forward + reverse sections)",
+                     "achieved": round(call_bytes / (ev_ms / args.steps * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(call_bytes / (ev_ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "note": "algorithmic bytes per call = batch x (6 S + 3) x 2^n x es"},
+    }
+    if not args.skip_cpu:
+        import oracle
+        ns, ls = 14, 40
+        tm = W.hardware_efficient_ansatz(ns, ls)
+        th = W.ansatz_parameters(ns, ls, 1, args.seed)[0]
+        ts = [(1.0, (1 << i) | (1 << ((i + 1) % ns))) for i in range(ns)]
+        t0 = time.perf_counter()
+        reps = 0
+        while reps == 0 or time.perf_counter() - t0 < 10.0:
+            oracle.adjoint_gradient(ns, tm, th, ts)
+            reps += 1
+        dt_cpu = (time.perf_counter() - t0) / reps
+        t_one = dt_cpu * float(1 << (n - ns))
+        rec["cpu_baseline"] = {"value": round(1.0 / t_one, 5), "unit": "gradients/s",
+                               "cores": blas_threads(), "kind": "oracle",
+                               "sample": "oracle adjoint gradient of a 14-qubit 40-layer ansatz, %d "
+                                         "evaluation(s) in %.1f s, scaled x2^6 amplitudes "
+                                         "(extrapolated %.1f s per 20-qubit gradient)"
+                                         % (reps, dt_cpu * reps, t_one)}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -107,6 +254,11 @@ def main():
     import torch
     from paper_2102_02957_amd import binding as B
     from paper_2102_02957_amd import workloads as W
+
+    if args.workload == "trajectories":
+        return bench_trajectories(args, torch, B, W)
+    if args.workload == "adjoint":
+        return bench_adjoint(args, torch, B, W)
 
     n = args.n
     dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64

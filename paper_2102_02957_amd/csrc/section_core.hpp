@@ -348,8 +348,8 @@ __device__ __forceinline__ void gather_scatter_barrier() {
     __builtin_amdgcn_s_barrier();
 }
 
-// Workgroup barrier that orders LDS accesses only: outstanding global loads
-// (the next chunk's prefetch) stay in flight across it.
+// Workgroup barrier that orders LDS accesses only: outstanding global stores
+// and loads are not waited for.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();

@@ -18,8 +18,6 @@
 // to a physical bit of the amplitude index.
 #pragma once
 
-#include <cstdlib>
-
 #include "section_core.hpp"
 
 namespace qsv {
@@ -47,65 +45,6 @@ k_section(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__res
                           reinterpret_cast<V *>(lds_raw), true);
 }
 
-// Persistent, software-pipelined variant for large states: each workgroup
-// walks a run of chunks, and the HBM gather of chunk i+1 is issued before the
-// register/LDS work on chunk i, so loads stay in flight under the compute
-// (barriers inside the phases order LDS only).  Workgroups are spread over
-// the 8 XCDs so that one XCD streams a contiguous range of chunk ids
-// (neighbouring chunks share cache lines when few low bits are pinned).
-template <typename T, int R, int KMAX, bool DENSE_ONLY>
-__global__ void __launch_bounds__(256)
-k_section_pipe(typename Amp<T>::V *__restrict__ state, int n,
-               const DevSection *__restrict__ secs_g, int sec,
-               const DevPhase *__restrict__ phases_g, const DevOp *__restrict__ ops_g,
-               const typename Amp<T>::V *__restrict__ mats_g,
-               const typename Amp<T>::V *__restrict__ ptab_g, int nslots, uint64_t nchunks) {
-    using V = typename Amp<T>::V;
-    extern __shared__ unsigned char lds_raw[];
-    V *lds = reinterpret_cast<V *>(lds_raw);
-    V *st = state + ((uint64_t)blockIdx.y << n);
-    const cptr<V> ptab = (cptr<V>)ptab_g + (size_t)blockIdx.y * 2 * nslots;
-    const cptr<DevSection> S = (cptr<DevSection>)secs_g + sec;
-    const cptr<DevPhase> ph = (cptr<DevPhase>)phases_g + S->phase_begin;
-    const cptr<DevOp> ops = (cptr<DevOp>)ops_g;
-    const cptr<V> mats = (cptr<V>)mats_g;
-    const int nph = (int)(S->phase_end - S->phase_begin);
-    const int TB = (int)S->c - R;
-    const unsigned tid = threadIdx.x;
-
-    // gridDim.x and nchunks are multiples of 8 (host guarantees)
-    const uint64_t per_xcd = nchunks >> 3;
-    const uint32_t xcd = blockIdx.x & 7u, w = blockIdx.x >> 3, stride = gridDim.x >> 3;
-    uint64_t g = (uint64_t)xcd * per_xcd + w;
-    const uint64_t g_end = (uint64_t)(xcd + 1) * per_xcd;
-    if (g >= g_end) return;
-
-    V a[1 << R], nx[1 << R];
-    uint64_t base = chunk_base(S, g);
-    chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
-    // Complete the first gather here: the wait-count bookkeeping merges the loop
-    // entry with the back edge, and loads still pending on a[] at entry would
-    // make every iteration wait for its own prefetch before the first LDS write.
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    for (;;) {
-        const uint64_t gn = g + stride;
-        const bool more = gn < g_end;
-        uint64_t base_n = 0;
-        if (more) {
-            base_n = chunk_base(S, gn);
-            chunk_gather<V, R>(nx, st, S->gather_phys, base_n, tid, TB);
-        }
-        chunk_phases<T, R, KMAX, DENSE_ONLY>(a, ph, nph, ops, mats, ptab, base, lds, TB, true);
-        if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
-        chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
-        if (!more) break;
-        static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) { a[I.value] = nx[I.value]; });
-        base = base_n;
-        g = gn;
-        if (nph > 1) lds_barrier();  // the next chunk's first LDS write follows this chunk's reads
-    }
-}
-
 template <typename T, int R, int KMAX, bool DENSE_ONLY>
 inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv, int sec, int c,
                                    size_t lds_bytes, const void *ptab, int nslots,
@@ -116,48 +55,11 @@ inline hipError_t launch_section_t(void *state, int n, int batch, DevPlanView pv
         hipError_t e = hipFuncSetAttribute((const void *)k_section<T, R, KMAX, DENSE_ONLY>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        if constexpr (R >= 4 && KMAX == 2) {
-            e = hipFuncSetAttribute((const void *)k_section_pipe<T, R, KMAX, DENSE_ONLY>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            if (e != hipSuccess) return e;
-        }
         attr_set = true;
     }
     if ((1 << (c - R)) > section_max_threads<R>() || c < R) return hipErrorInvalidConfiguration;
     const uint64_t nchunks = 1ull << (n - c);
     dim3 block(1u << (c - R));
-    // persistent pipelined kernel when every resident workgroup gets >= 2 chunks
-    static int resident = -1;
-    static size_t resident_lds = (size_t)-1;
-    if constexpr (R >= 4 && KMAX == 2) {
-        if (resident < 0 || resident_lds != lds_bytes) {
-            int per_cu = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, k_section_pipe<T, R, KMAX, DENSE_ONLY>, (int)block.x, lds_bytes) !=
-                hipSuccess)
-                per_cu = 0;
-            int dev = 0, cus = 0;
-            (void)hipGetDevice(&dev);
-            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            resident = per_cu * cus;
-            resident_lds = lds_bytes;
-        }
-    }
-    const uint64_t G = ((uint64_t)resident / 8) * 8;
-    // the prefetching variant needs twice the amplitude registers, which halves
-    // occupancy; it is opt-in (QSV_SECTION_PIPE=1) until it wins
-    static const bool pipe_on = [] {
-        const char *e = getenv("QSV_SECTION_PIPE");
-        return e && e[0] == '1';
-    }();
-    if constexpr (R >= 4 && KMAX == 2) {
-      if (pipe_on && batch == 1 && c - R <= 8 && G >= 8 && nchunks >= 2 * G && nchunks % 8 == 0) {
-        hipLaunchKernelGGL((k_section_pipe<T, R, KMAX, DENSE_ONLY>), dim3((unsigned)G, 1), block, lds_bytes, s,
-                           (V *)state, n, pv.secs, sec, pv.phases, pv.ops, (const V *)pv.mats,
-                           (const V *)ptab, nslots, nchunks);
-        return hipGetLastError();
-      }
-    }
     dim3 grid((unsigned)nchunks, (unsigned)batch);
     hipLaunchKernelGGL((k_section<T, R, KMAX, DENSE_ONLY>), grid, block, lds_bytes, s, (V *)state, n, pv.secs,
                        sec, pv.phases, pv.ops, (const V *)pv.mats, (const V *)ptab, nslots);

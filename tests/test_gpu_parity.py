@@ -156,6 +156,16 @@ def test_qv_512_thread_sections(torch, ctxs, dt):
 
 
 @pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_io_phases_option(torch, ctxs, dt):
+    """io_phases = 1: sections gather/scatter through an extra op-free phase
+    in the coalesced map (applies when the state has >= 2^8 chunks)."""
+    n = 21
+    for gates in (W.quantum_volume(n, 6, 8), W.random_circuit(n, 120, 13, max_unitary_qubits=2)):
+        got, plan = run_gpu(torch, ctxs, n, gates, dt, chunk_bits=12, io_phases=1)
+        assert_close(got, oracle.apply_circuit(n, gates), dt, "io_phases")
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
 def test_swap_only_sections_in_place(torch, ctxs, dt):
     """SWAP-only sections: one phase, no transposition, amplitudes change
     thread (and wave) between the gather and the in-place scatter.  Bit-exact,
