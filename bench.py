@@ -153,7 +153,7 @@ def bench_trajectories(args, torch, B, W):
                                "complex64, seed %d" % args.seed,
                    "gates": gates, "states_mib": round(o * 8 / 2 ** 20, 1), "plan_s": round(t_plan, 3)},
         "gates_per_s": round(gates * args.steps / wall, 1),
-        "roofline": {"bound": "hbm", "kernel": "batch graph (k_batch_init, k_batch, k_batch_scale)",
+        "roofline": {"bound": "hbm", "kernel": "batch graph (k_batch_init, k_batch_step per depth, k_batch_norms, k_batch_scale)",
                      "achieved": round(step_bytes / (ev_ms / args.steps * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(step_bytes / (ev_ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -224,9 +224,10 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm 
 /* Run `count` independent circuits (e.g. noisy trajectories with sampled Pauli
  * insertions), each on its own state of n_b qubits stored at states + offsets[b]
  * amplitudes (offsets: host array; states must not overlap and must start on 256-byte
- * boundaries), in one launch: every state is set to |0>, one workgroup walks all
- * sections and chunks of its plan (largest states first), accumulates the FP64 norm of
- * the final state, and every state is rescaled by 1/sqrt(norm).  norms_dev[b] receives
+ * boundaries), in one graph launch: every state is set to |0>; then, for each section
+ * depth d, one kernel runs section d of every plan that has one, a workgroup per
+ * (state, chunk); the last section of each plan writes per-chunk FP64 norms, reduced in
+ * chunk order, and every state is rescaled by 1/sqrt(norm).  norms_dev[b] receives
  * <psi_b|psi_b> before the rescale.  The sequence is captured into a HIP graph on the
  * first call for a given (plans, offsets, states, norms_dev) and replayed afterwards.
  * Plans: same dtype as the context, remap mode, no bound parameters, equal

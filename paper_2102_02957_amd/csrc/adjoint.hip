@@ -206,7 +206,6 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
     using V = typename Amp<T>::V;
     extern __shared__ unsigned char lds_raw[];
     V *lds = reinterpret_cast<V *>(lds_raw);
-    __shared__ double wsum[4];
     __shared__ double red[64];
     const unsigned tid = threadIdx.x;
     const uint64_t chunk = blockIdx.x, nchunks = gridDim.x;
@@ -223,6 +222,11 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
     const uint64_t base = chunk_base(S, chunk);
     const uint32_t pbase = tid << R;
     const int nwaves = (int)(blockDim.x + 63) / 64;
+    // per-wave gradient partials of this section's parameterised ops, after the
+    // chunk's transposition area: wpart[(slot - param_slot) * nwaves + wave]
+    const size_t chunk_bytes = nph > 1 ? (sizeof(V) << S->c) : 0;
+    double *wpart = reinterpret_cast<double *>(lds_raw + chunk_bytes);
+    const bool whole_waves = blockDim.x >= 64;
 
     V psi[1 << R], lam[1 << R];
     chunk_gather<V, R>(psi, psi_st, S->scatter_phys, base, tid, TB);
@@ -234,28 +238,34 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
             op_inverse<T, R, KMAX>(psi, op, mats, ptab, pbase, base);
             if (op.type == OP_PROT || op.type == OP_PDIAG) {
                 const double g = op_dgrad<T, R>(psi, lam, op, ptab, pbase, base);
-                double total;
-                if (blockDim.x >= 64) {
+                if (whole_waves) {
+                    // wave sum now, cross-wave sum once per section (no barrier here)
                     const double w = wave_sum(g);
-                    if ((tid & 63) == 0) wsum[tid >> 6] = w;
-                    __syncthreads();
-                    total = 0.0;
-                    for (int w2 = 0; w2 < nwaves; ++w2) total += wsum[w2];
+                    if ((tid & 63) == 0)
+                        wpart[(size_t)(op.slot - (int32_t)S->param_slot) * nwaves + (tid >> 6)] = w;
                 } else {
                     // partial wave: fixed-order sum through LDS
                     red[tid] = g;
                     __syncthreads();
-                    total = 0.0;
+                    double total = 0.0;
                     for (unsigned t = 0; t < blockDim.x; ++t) total += red[t];
+                    if (tid == 0) part[((size_t)b * nslots + op.slot) * nchunks + chunk] = total;
+                    __syncthreads();
                 }
-                if (tid == 0) part[((size_t)b * nslots + op.slot) * nchunks + chunk] = total;
-                __syncthreads();
             }
             op_inverse<T, R, KMAX>(lam, op, mats, ptab, pbase, base);
         }
         if (p > 0) {
             chunk_transpose<V, R>(psi, lds, P->rd, ph[p - 1].wr, tid, TB, true);
             chunk_transpose<V, R>(lam, lds, P->rd, ph[p - 1].wr, tid, TB, true);
+        }
+    }
+    if (whole_waves && S->n_params_used > 0) {
+        __syncthreads();
+        for (uint32_t i = tid; i < S->n_params_used; i += blockDim.x) {
+            double total = 0.0;
+            for (int w = 0; w < nwaves; ++w) total += wpart[(size_t)i * nwaves + w];
+            part[((size_t)b * nslots + S->param_slot + i) * nchunks + chunk] = total;
         }
     }
     if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
@@ -307,6 +317,9 @@ k_param_grads(const double *__restrict__ ssum, const int32_t *__restrict__ off,
     grad[i] = s;
 }
 
+// dynamic LDS limit of the reverse-section kernel (160 KiB less its static part)
+constexpr size_t ADJ_MAX_DYN_LDS = 159 * 1024;
+
 template <typename T, int R, int KMAX>
 static hipError_t adj_launch_t(void *psi, void *lam, int n, int batch, DevPlanView pv, int sec,
                                int c, size_t lds, const void *ptab, int nslots, double *part,
@@ -315,11 +328,12 @@ static hipError_t adj_launch_t(void *psi, void *lam, int n, int batch, DevPlanVi
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)k_adjoint_section<T, R, KMAX>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           ADJ_MAX_DYN_LDS);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    if (c - R > 8 || c < R) return hipErrorInvalidConfiguration;
+    if (c - R > 8 || c < R || lds > ADJ_MAX_DYN_LDS) return hipErrorInvalidConfiguration;
     dim3 grid((unsigned)(1ull << (n - c)), (unsigned)batch);
     hipLaunchKernelGGL((k_adjoint_section<T, R, KMAX>), grid, dim3(1u << (c - R)), lds, s,
                        (V *)psi, (V *)lam, n, pv.secs, sec, pv.phases, pv.ops, (const V *)pv.mats,

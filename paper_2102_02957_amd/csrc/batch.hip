@@ -1,14 +1,15 @@
 // Batched trajectories: many independent states of uneven qubit counts (the
-// paper's shots / noisy simulation, Sec. III-A and IV-B) run in one launch.
+// paper's shots / noisy simulation, Sec. III-A and IV-B) in one graph launch.
 //
-// One workgroup owns one whole trajectory: it walks every section of that
-// trajectory's plan and, inside a section, every chunk, so no workgroup ever
-// waits on another (no cross-workgroup counters, nothing to spin on).
-// Workgroups take trajectories largest first, so the long ones start at once.
-// The last section also accumulates the state's FP64 norm in chunk order; a
-// second kernel rescales every state by 1/sqrt(norm).  The whole sequence
-// (init, trajectory kernel, rescale) is captured once into a HIP graph and
-// replayed.
+// Section depth d of every trajectory that has one runs in one kernel: a
+// workgroup per (trajectory, chunk) of that section, so a large trajectory's
+// chunks spread over the whole GPU while small trajectories (one chunk, one
+// section) finish in the first kernel.  Consecutive depths are ordered by the
+// kernel boundaries of the graph (no workgroup ever waits on another).  The
+// last section of a trajectory writes each chunk's FP64 norm; a reduction in
+// chunk order gives the state's norm and a final kernel rescales every state by
+// 1/sqrt(norm).  The whole sequence (init, depth kernels, norms, rescale) is
+// captured once into a HIP graph and replayed.
 #include <cstring>
 #include <map>
 #include <memory>
@@ -29,49 +30,57 @@ struct BatchTraj {        // one trajectory (state) of the batch
     uint32_t sec_begin;   // first section in the combined section table
     uint32_t nsec;
     uint32_t nchunks;     // chunks per section
-    uint32_t pad[2];
+    uint32_t part_off;    // first of its per-chunk norm partials
+    uint32_t pad;
+};
+
+struct BatchItem {       // one workgroup of a depth kernel
+    uint32_t traj;
+    uint32_t chunk;
 };
 
 
 constexpr int BATCH_THREADS = 256;
 
+// Section `depth` of every trajectory listed in items: one workgroup per
+// (trajectory, chunk).
 template <typename T, int R, int KMAX>
 __global__ void __launch_bounds__(BATCH_THREADS)
-k_batch(typename Amp<T>::V *__restrict__ states, const BatchTraj *__restrict__ trajs,
-        const uint32_t *__restrict__ order, double *__restrict__ norms,
-        const DevSection *__restrict__ secs_g, const DevPhase *__restrict__ phases_g,
-        const DevOp *__restrict__ ops_g, const typename Amp<T>::V *__restrict__ mats_g) {
+k_batch_step(typename Amp<T>::V *__restrict__ states, const BatchTraj *__restrict__ trajs,
+             const BatchItem *__restrict__ items, uint32_t depth, double *__restrict__ partials,
+             const DevSection *__restrict__ secs_g, const DevPhase *__restrict__ phases_g,
+             const DevOp *__restrict__ ops_g, const typename Amp<T>::V *__restrict__ mats_g) {
     using V = typename Amp<T>::V;
     extern __shared__ unsigned char lds_raw[];
     V *lds = reinterpret_cast<V *>(lds_raw);
     __shared__ double s_red[BATCH_THREADS];
     const unsigned tid = threadIdx.x;
-    const uint32_t b = order[blockIdx.x];
-    const BatchTraj tr = trajs[b];
+    const BatchItem it = items[blockIdx.x];
+    const BatchTraj tr = trajs[it.traj];
     V *st = states + tr.state_off;
-    double norm = 0.0;
-    for (uint32_t s = 0; s < tr.nsec; ++s) {
-        const cptr<DevSection> S = (cptr<DevSection>)secs_g + (tr.sec_begin + s);
-        const bool active = tid < (1u << (S->c - R));
-        const bool last = s + 1 == tr.nsec;
-        for (uint32_t g = 0; g < tr.nchunks; ++g) {
-            if (last) {
-                norm += run_chunk_norm<T, R, KMAX>(st, S, (cptr<DevPhase>)phases_g,
-                                                   (cptr<DevOp>)ops_g, (cptr<V>)mats_g, nullptr,
-                                                   g, lds, s_red, active);
-            } else {
-                run_chunk<T, R, KMAX>(st, S, (cptr<DevPhase>)phases_g, (cptr<DevOp>)ops_g,
-                                      (cptr<V>)mats_g, nullptr, g, lds, active);
-            }
-        }
-        if (!last) {
-            // the next section gathers what this workgroup's waves just scattered
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        }
+    const cptr<DevSection> S = (cptr<DevSection>)secs_g + (tr.sec_begin + depth);
+    const bool active = tid < (1u << (S->c - R));
+    if (depth + 1 == tr.nsec) {
+        const double nrm = run_chunk_norm<T, R, KMAX>(st, S, (cptr<DevPhase>)phases_g,
+                                                      (cptr<DevOp>)ops_g, (cptr<V>)mats_g, nullptr,
+                                                      it.chunk, lds, s_red, active);
+        if (tid == 0) partials[tr.part_off + it.chunk] = nrm;
+    } else {
+        run_chunk<T, R, KMAX>(st, S, (cptr<DevPhase>)phases_g, (cptr<DevOp>)ops_g,
+                              (cptr<V>)mats_g, nullptr, it.chunk, lds, active);
     }
-    if (tid == 0) norms[b] = norm;
+}
+
+// norms[b] = sum of trajectory b's chunk partials, in chunk order
+__global__ void __launch_bounds__(256)
+k_batch_norms(const BatchTraj *__restrict__ trajs, const double *__restrict__ partials,
+              double *__restrict__ norms, int count) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= count) return;
+    const BatchTraj tr = trajs[b];
+    double s = 0.0;
+    for (uint32_t g = 0; g < tr.nchunks; ++g) s += partials[tr.part_off + g];
+    norms[b] = s;
 }
 
 // states *= 1/sqrt(norm) (FP64 scale), one workgroup per (trajectory, block of 2^12 amplitudes)
@@ -131,35 +140,37 @@ k_batch_ones(V *__restrict__ states, const BatchTraj *__restrict__ trajs, int co
 #include "batch.hpp"
 namespace qsv {
 
-static hipError_t launch_batch_kernel(qsv_dtype dt, const BatchLaunch &L, hipStream_t s);
+static hipError_t launch_batch_kernel(qsv_dtype dt, const BatchLaunch &L, uint32_t depth,
+                                      hipStream_t s);
 
 template <typename T, int R, int KMAX>
-static hipError_t launch_batch_t(const BatchLaunch &L, hipStream_t s) {
+static hipError_t launch_batch_t(const BatchLaunch &L, uint32_t depth, hipStream_t s) {
     using V = typename Amp<T>::V;
     if (!s) {  // setup call (outside any stream capture)
-        return hipFuncSetAttribute((const void *)k_batch<T, R, KMAX>,
+        return hipFuncSetAttribute((const void *)k_batch_step<T, R, KMAX>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
     }
-    hipLaunchKernelGGL((k_batch<T, R, KMAX>), dim3(L.count), dim3(BATCH_THREADS), L.lds, s,
-                       (V *)L.states, L.trajs, L.order, L.norms, L.secs, L.phases, L.ops,
-                       (const V *)L.mats);
+    hipLaunchKernelGGL((k_batch_step<T, R, KMAX>), dim3(L.depth_count[depth]), dim3(BATCH_THREADS),
+                       L.lds, s, (V *)L.states, L.trajs, L.items + L.depth_off[depth], depth,
+                       L.partials, L.secs, L.phases, L.ops, (const V *)L.mats);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_batch_dt(const BatchLaunch &L, hipStream_t s) {
+static hipError_t launch_batch_dt(const BatchLaunch &L, uint32_t depth, hipStream_t s) {
     const bool wide = L.kmax > 2;
     switch (L.r) {
-        case 3: return wide ? launch_batch_t<T, 3, 3>(L, s) : launch_batch_t<T, 3, 2>(L, s);
-        case 4: return wide ? launch_batch_t<T, 4, 4>(L, s) : launch_batch_t<T, 4, 2>(L, s);
-        case 5: return wide ? launch_batch_t<T, 5, 5>(L, s) : launch_batch_t<T, 5, 2>(L, s);
+        case 3: return wide ? launch_batch_t<T, 3, 3>(L, depth, s) : launch_batch_t<T, 3, 2>(L, depth, s);
+        case 4: return wide ? launch_batch_t<T, 4, 4>(L, depth, s) : launch_batch_t<T, 4, 2>(L, depth, s);
+        case 5: return wide ? launch_batch_t<T, 5, 5>(L, depth, s) : launch_batch_t<T, 5, 2>(L, depth, s);
     }
     return hipErrorInvalidValue;
 }
 
-static hipError_t launch_batch_kernel(qsv_dtype dt, const BatchLaunch &L, hipStream_t s) {
-    if (dt == QSV_C128) return launch_batch_dt<double>(L, s);
-    return launch_batch_dt<float>(L, s);
+static hipError_t launch_batch_kernel(qsv_dtype dt, const BatchLaunch &L, uint32_t depth,
+                                      hipStream_t s) {
+    if (dt == QSV_C128) return launch_batch_dt<double>(L, depth, s);
+    return launch_batch_dt<float>(L, depth, s);
 }
 
 // Build (or fetch) the batch launch for these plans/buffers; captures the graph.
@@ -177,6 +188,7 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
     std::vector<cd> mats;
     uint32_t maxS = 0;
     uint64_t total = 0;
+    uint64_t npart = 0;
     for (int b = 0; b < count; ++b) {
         const Plan &P = *plans[b];
         if (P.dtype != dt) {
@@ -206,6 +218,9 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
         t.sec_begin = (uint32_t)secs.size();
         t.nsec = (uint32_t)P.dsec.size();
         t.nchunks = (uint32_t)(1ull << (P.n - P.c));
+        t.part_off = (uint32_t)npart;
+        t.pad = 0;
+        npart += t.nchunks;
         maxS = std::max(maxS, t.nsec);
         total = std::max<uint64_t>(total, offsets[b] + (1ull << P.n));
         const uint32_t ph0 = (uint32_t)phases.size(), op0 = (uint32_t)ops.size(),
@@ -246,6 +261,17 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
     for (int k = 0; k < count; ++k) order[k] = (uint32_t)k;
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t x, uint32_t y) { return trajs[x].n > trajs[y].n; });
+    // work items of each section depth: (trajectory, chunk), largest trajectories first
+    std::vector<BatchItem> items;
+    L.depth_off.assign(maxS, 0);
+    L.depth_count.assign(maxS, 0);
+    for (uint32_t d = 0; d < maxS; ++d) {
+        L.depth_off[d] = (uint32_t)items.size();
+        for (uint32_t b : order)
+            if (d < trajs[b].nsec)
+                for (uint32_t g = 0; g < trajs[b].nchunks; ++g) items.push_back({b, g});
+        L.depth_count[d] = (uint32_t)items.size() - L.depth_off[d];
+    }
     std::vector<ScaleBlock> sblocks;
     for (int b = 0; b < count; ++b) {
         uint64_t nb = ((1ull << trajs[b].n) + 4095) >> 12;
@@ -254,17 +280,18 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
 
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     size_t o_tr = 0;
-    size_t o_or = align(o_tr + trajs.size() * sizeof(BatchTraj));
-    size_t o_sb = align(o_or + order.size() * sizeof(uint32_t));
-    size_t o_se = align(o_sb + sblocks.size() * sizeof(ScaleBlock));
+    size_t o_sb = align(o_tr + trajs.size() * sizeof(BatchTraj));
+    size_t o_it = align(o_sb + sblocks.size() * sizeof(ScaleBlock));
+    size_t o_pa = align(o_it + items.size() * sizeof(BatchItem));
+    size_t o_se = align(o_pa + npart * sizeof(double));
     size_t o_ph = align(o_se + secs.size() * sizeof(DevSection));
     size_t o_op = align(o_ph + phases.size() * sizeof(DevPhase));
     size_t o_m = align(o_op + ops.size() * sizeof(DevOp));
     size_t tot = align(o_m + mats.size() * es) + 256;
     std::vector<unsigned char> host(tot, 0);
     std::memcpy(host.data() + o_tr, trajs.data(), trajs.size() * sizeof(BatchTraj));
-    std::memcpy(host.data() + o_or, order.data(), order.size() * sizeof(uint32_t));
     std::memcpy(host.data() + o_sb, sblocks.data(), sblocks.size() * sizeof(ScaleBlock));
+    std::memcpy(host.data() + o_it, items.data(), items.size() * sizeof(BatchItem));
     std::memcpy(host.data() + o_se, secs.data(), secs.size() * sizeof(DevSection));
     std::memcpy(host.data() + o_ph, phases.data(), phases.size() * sizeof(DevPhase));
     std::memcpy(host.data() + o_op, ops.data(), ops.size() * sizeof(DevOp));
@@ -289,8 +316,9 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
     }
     unsigned char *base = (unsigned char *)L.block;
     L.trajs = (BatchTraj *)(base + o_tr);
-    L.order = (uint32_t *)(base + o_or);
     L.sblocks = (ScaleBlock *)(base + o_sb);
+    L.items = (BatchItem *)(base + o_it);
+    L.partials = (double *)(base + o_pa);
     L.secs = (DevSection *)(base + o_se);
     L.phases = (DevPhase *)(base + o_ph);
     L.ops = (DevOp *)(base + o_op);
@@ -302,7 +330,7 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
     L.kmax = kmax;
     L.lds = lds;
     {
-        hipError_t ea = launch_batch_kernel(dt, L, nullptr);  // attributes only
+        hipError_t ea = launch_batch_kernel(dt, L, 0, nullptr);  // attributes only
         if (ea != hipSuccess) {
             err = std::string("batch kernel setup: ") + hipGetErrorString(ea);
             return QSV_E_HIP;
@@ -311,7 +339,7 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
     L.states = states;
     L.norms = norms;
 
-    // capture: init, trajectory kernel, rescale
+    // capture: init, one kernel per section depth, norms, rescale
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -332,7 +360,10 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
             hipLaunchKernelGGL((k_batch_ones<Cplx<float>>), dim3((count + 255) / 256), dim3(256),
                                0, cs, (Cplx<float> *)states, L.trajs, count);
         }
-        (void)launch_batch_kernel(dt, L, cs);
+        for (uint32_t d = 0; d < maxS; ++d)
+            if (L.depth_count[d] > 0) (void)launch_batch_kernel(dt, L, d, cs);
+        hipLaunchKernelGGL(k_batch_norms, dim3((count + 255) / 256), dim3(256), 0, cs, L.trajs,
+                           L.partials, norms, count);
         if (dt == QSV_C128)
             hipLaunchKernelGGL((k_batch_scale<Cplx<double>>), dim3(L.nsblocks), dim3(256), 0, cs,
                                (Cplx<double> *)states, L.trajs, L.sblocks, norms);

@@ -4,19 +4,23 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "qsv_internal.hpp"
 
 namespace qsv {
 
 struct BatchTraj;
+struct BatchItem;
 struct ScaleBlock;
 
 struct BatchLaunch {
     void *block = nullptr;          // one device allocation holding every table below
     BatchTraj *trajs = nullptr;
-    uint32_t *order = nullptr;      // trajectory of workgroup k (largest first)
     ScaleBlock *sblocks = nullptr;
+    BatchItem *items = nullptr;     // (trajectory, chunk) work items of every depth
+    double *partials = nullptr;     // per-chunk FP64 norms of the last sections
+    std::vector<uint32_t> depth_off, depth_count;  // items of depth d (host)
     DevSection *secs = nullptr;
     DevPhase *phases = nullptr;
     DevOp *ops = nullptr;
@@ -32,7 +36,7 @@ struct BatchLaunch {
 };
 
 // Build the combined tables for these plans, upload them and capture the graph
-// (|0> init, trajectory kernel, rescale).
+// (|0> init, one kernel per section depth, norms, rescale).
 qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
                          const uint64_t *offsets, void *states, double *norms,
                          BatchLaunch &L, std::string &err);

@@ -851,7 +851,14 @@ extern "C" qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const
     double *part = ctx->partials;
     double *ssum = ctx->partials + (size_t)batch * nslots * nchunks;
     for (int64_t si = (int64_t)P.sections.size() - 1; si >= 0; --si) {
-        const size_t lds = section_lds(P, (int)si);
+        // transposition area + per-wave gradient partials of the section's ops
+        const size_t waves = ((size_t(1) << (P.dsec[si].c - P.r)) + 63) / 64;
+        const size_t lds = section_lds(P, (int)si) + P.dsec[si].n_params_used * waves * sizeof(double);
+        if (lds > 159 * 1024) {
+            set_error("adjoint: section " + std::to_string(si) + " has too many parameterised "
+                      "ops for the reverse sweep's LDS (use smaller chunks)");
+            return QSV_E_UNSUPPORTED;
+        }
         rc = timed(ctx, 0, s, [&] {
             return launch_adjoint_section(P.dtype, P.r, psi_dev, lambda_dev, n, batch, *pv, (int)si,
                                           P.c, lds, ctx->ptab, nslots, part, s);
