@@ -285,6 +285,33 @@ __device__ __forceinline__ unsigned src_bit(unsigned s, uint32_t pidx, uint64_t 
     return s >= SRC_GLOBAL ? (unsigned)((base >> (s - SRC_GLOBAL)) & 1ull) : ((pidx >> s) & 1u);
 }
 
+// LDS byte address (t ^ u) + base as one VALU op (v_xad_u32): t per lane, u
+// uniform, base the LDS buffer's address.  Written as inline asm so that the
+// byte scaling folded into t and u is not factored back out of the XOR.
+__device__ __forceinline__ uint32_t lds_xad(uint32_t t, uint32_t u, uint32_t base) {
+    uint32_t r;
+    asm("v_xad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(t), "s"(u), "v"(base));
+    return r;
+}
+// one amplitude to / from an LDS byte address (a single 8- or 16-byte access)
+template <typename V> __device__ __forceinline__ void lds_put(uint32_t addr, const V &v) {
+    using E = decltype(v.x);
+    typedef E __attribute__((ext_vector_type(2))) E2;
+    E2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *(__attribute__((address_space(3))) E2 *)(uintptr_t)addr = w;
+}
+template <typename V> __device__ __forceinline__ V lds_get(uint32_t addr) {
+    using E = decltype(V{}.x);
+    typedef E __attribute__((ext_vector_type(2))) E2;
+    const E2 w = *(__attribute__((address_space(3))) E2 *)(uintptr_t)addr;
+    V v;
+    v.x = w.x;
+    v.y = w.y;
+    return v;
+}
+
 // LDS bank swizzle: XOR-fold the higher index bits into the bank-selecting low
 // bits (128 B rows).  The map is linear over GF(2), swz(x ^ y) = swz(x) ^ swz(y),
 // so the address of every element is the thread's swizzled part XOR a uniform
@@ -370,19 +397,24 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
             tr |= ((tid >> B.value) & 1u) << to[R + B.value];
         }
     });
-    // byte offsets: thread part (per lane) ^ register part (uniform)
-    char *lb = reinterpret_cast<char *>(lds);
+    // byte offsets: thread part (per lane) ^ register part (uniform, one scalar
+    // value per register bit, combined per element)
+    const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)lds;
     const uint32_t tws = lds_swizzle<V>(tw) * (uint32_t)sizeof(V);
     const uint32_t trs = lds_swizzle<V>(tr) * (uint32_t)sizeof(V);
+    uint32_t sw[R], sr[R];
+    static_for<R>([&](auto B) __attribute__((always_inline)) {
+        sw[B.value] = lds_swizzle<V>(1u << from[B.value]) * (uint32_t)sizeof(V);
+        sr[B.value] = lds_swizzle<V>(1u << to[B.value]) * (uint32_t)sizeof(V);
+    });
     lds_barrier();
     if (active) {
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
             uint32_t u = 0;
             static_for<R>([&](auto B) __attribute__((always_inline)) {
-                if constexpr (((I.value >> B.value) & 1) != 0)
-                    u ^= lds_swizzle<V>(1u << from[B.value]) * (uint32_t)sizeof(V);
+                if constexpr (((I.value >> B.value) & 1) != 0) u ^= sw[B.value];
             });
-            *reinterpret_cast<V *>(lb + (tws ^ u)) = a[I.value];
+            lds_put<V>(lds_xad(tws, u, lbase), a[I.value]);
         });
     }
     lds_barrier();
@@ -390,10 +422,9 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
         static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
             uint32_t u = 0;
             static_for<R>([&](auto B) __attribute__((always_inline)) {
-                if constexpr (((I.value >> B.value) & 1) != 0)
-                    u ^= lds_swizzle<V>(1u << to[B.value]) * (uint32_t)sizeof(V);
+                if constexpr (((I.value >> B.value) & 1) != 0) u ^= sr[B.value];
             });
-            a[I.value] = *reinterpret_cast<const V *>(lb + (trs ^ u));
+            a[I.value] = lds_get<V>(lds_xad(trs, u, lbase));
         });
     }
 }
