@@ -230,7 +230,7 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
             d.phase_begin += ph0;
             d.phase_end += ph0;
             secs.push_back(d);
-            if (d.phase_end - d.phase_begin > 1) lds = std::max(lds, (size_t(1) << d.c) * es);
+            if (d.phase_end - d.phase_begin > 1) lds = std::max(lds, transpose_lds_bytes(d.c));
         }
         for (const DevPhase &p : P.dphase) {
             DevPhase q = p;

@@ -22,6 +22,11 @@ namespace qsv {
 
 using cd = std::complex<double>;
 
+// LDS transpositions move 8-byte elements (a complex128 amplitude in two
+// passes), so a section's transposition buffer is 2^c * 8 bytes for either type.
+constexpr unsigned TRANSPOSE_LDS_ELEM = 8;
+inline size_t transpose_lds_bytes(int c) { return (size_t(1) << c) * TRANSPOSE_LDS_ELEM; }
+
 // ---- device-side plan records (plain data, copied to the GPU) -------------
 
 // Bit source of a diagonal gate / CX control, resolved per section:

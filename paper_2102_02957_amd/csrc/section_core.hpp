@@ -293,7 +293,7 @@ __device__ __forceinline__ uint32_t lds_xad(uint32_t t, uint32_t u, uint32_t bas
     asm("v_xad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(t), "s"(u), "v"(base));
     return r;
 }
-// one amplitude to / from an LDS byte address (a single 8- or 16-byte access)
+// one 8-byte amplitude to / from an LDS byte address (a single access)
 template <typename V> __device__ __forceinline__ void lds_put(uint32_t addr, const V &v) {
     using E = decltype(v.x);
     typedef E __attribute__((ext_vector_type(2))) E2;
@@ -312,13 +312,12 @@ template <typename V> __device__ __forceinline__ V lds_get(uint32_t addr) {
     return v;
 }
 
-// LDS bank swizzle: XOR-fold the higher index bits into the bank-selecting low
-// bits (128 B rows).  The map is linear over GF(2), swz(x ^ y) = swz(x) ^ swz(y),
-// so the address of every element is the thread's swizzled part XOR a uniform
-// (scalar) swizzled register part.
-template <typename V> __device__ __forceinline__ uint32_t lds_swizzle(uint32_t j) {
-    if constexpr (sizeof(V) == 16) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7u);
-    else return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15u);
+// LDS bank swizzle of the index of an 8-byte element: XOR-fold the higher index
+// bits into the bank-selecting low bits (128 B rows).  The map is linear over
+// GF(2), swz(x ^ y) = swz(x) ^ swz(y), so the address of every element is the
+// thread's swizzled part XOR a uniform (scalar) swizzled register part.
+__device__ __forceinline__ uint32_t lds_swizzle(uint32_t j) {
+    return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15u);
 }
 
 
@@ -383,12 +382,20 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// LDS transposition from position->slot map `from` to map `to`.  Threads with
-// active == false take part in the barriers only.
+// LDS transposition from position->slot map `from` to map `to`, through a
+// buffer of 2^c 8-byte elements (TRANSPOSE_LDS_ELEM): a complex64 amplitude
+// moves whole, a complex128 amplitude in two passes, real parts then imaginary
+// parts.  Half the LDS of a whole-amplitude buffer lets a third complex128
+// workgroup share a CU at c = 12, which hides more HBM and barrier latency than
+// the two extra barriers cost.  Threads with active == false take part in the
+// barriers only.
 template <typename V, int R>
 __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uint8_t> from_tab,
                                                 cptr<uint8_t> to_tab, unsigned tid, int TB,
                                                 bool active) {
+    using E = decltype(V{}.x);
+    constexpr bool split = sizeof(V) == 2 * TRANSPOSE_LDS_ELEM;
+    static_assert(split || sizeof(V) == TRANSPOSE_LDS_ELEM, "8- or 16-byte amplitudes");
     const Bytes16 from = ld16(from_tab), to = ld16(to_tab);
     uint32_t tw = 0, tr = 0;
     static_for<9>([&](auto B) __attribute__((always_inline)) {
@@ -399,34 +406,49 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
     });
     // byte offsets: thread part (per lane) ^ register part (uniform, one scalar
     // value per register bit, combined per element)
+    constexpr uint32_t EB = TRANSPOSE_LDS_ELEM;
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)lds;
-    const uint32_t tws = lds_swizzle<V>(tw) * (uint32_t)sizeof(V);
-    const uint32_t trs = lds_swizzle<V>(tr) * (uint32_t)sizeof(V);
+    const uint32_t tws = lds_swizzle(tw) * EB;
+    const uint32_t trs = lds_swizzle(tr) * EB;
     uint32_t sw[R], sr[R];
     static_for<R>([&](auto B) __attribute__((always_inline)) {
-        sw[B.value] = lds_swizzle<V>(1u << from[B.value]) * (uint32_t)sizeof(V);
-        sr[B.value] = lds_swizzle<V>(1u << to[B.value]) * (uint32_t)sizeof(V);
+        sw[B.value] = lds_swizzle(1u << from[B.value]) * EB;
+        sr[B.value] = lds_swizzle(1u << to[B.value]) * EB;
     });
-    lds_barrier();
-    if (active) {
-        static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
-            uint32_t u = 0;
-            static_for<R>([&](auto B) __attribute__((always_inline)) {
-                if constexpr (((I.value >> B.value) & 1) != 0) u ^= sw[B.value];
+    static_for<split ? 2 : 1>([&](auto H) __attribute__((always_inline)) {
+        lds_barrier();  // the previous pass's reads are done before this pass writes
+        if (active) {
+            static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+                uint32_t u = 0;
+                static_for<R>([&](auto B) __attribute__((always_inline)) {
+                    if constexpr (((I.value >> B.value) & 1) != 0) u ^= sw[B.value];
+                });
+                const uint32_t addr = lds_xad(tws, u, lbase);
+                if constexpr (split)
+                    *(__attribute__((address_space(3))) E *)(uintptr_t)addr =
+                        H.value == 0 ? a[I.value].x : a[I.value].y;
+                else
+                    lds_put<V>(addr, a[I.value]);
             });
-            lds_put<V>(lds_xad(tws, u, lbase), a[I.value]);
-        });
-    }
-    lds_barrier();
-    if (active) {
-        static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
-            uint32_t u = 0;
-            static_for<R>([&](auto B) __attribute__((always_inline)) {
-                if constexpr (((I.value >> B.value) & 1) != 0) u ^= sr[B.value];
+        }
+        lds_barrier();
+        if (active) {
+            static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
+                uint32_t u = 0;
+                static_for<R>([&](auto B) __attribute__((always_inline)) {
+                    if constexpr (((I.value >> B.value) & 1) != 0) u ^= sr[B.value];
+                });
+                const uint32_t addr = lds_xad(trs, u, lbase);
+                if constexpr (split) {
+                    const E v = *(__attribute__((address_space(3))) E *)(uintptr_t)addr;
+                    if constexpr (H.value == 0) a[I.value].x = v;
+                    else a[I.value].y = v;
+                } else {
+                    a[I.value] = lds_get<V>(addr);
+                }
             });
-            a[I.value] = lds_get<V>(lds_xad(trs, u, lbase));
-        });
-    }
+        }
+    });
 }
 
 // Forward application of the ops [o_begin, o_end) of one phase to the
