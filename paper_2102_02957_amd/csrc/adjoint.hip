@@ -224,7 +224,7 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
     const int nwaves = (int)(blockDim.x + 63) / 64;
     // per-wave gradient partials of this section's parameterised ops, after the
     // chunk's transposition area: wpart[(slot - param_slot) * nwaves + wave]
-    const size_t chunk_bytes = nph > 1 ? ((size_t)TRANSPOSE_LDS_ELEM << S->c) : 0;
+    const size_t chunk_bytes = nph > 1 ? ((sizeof(V) / 2) << S->c) : 0;
     double *wpart = reinterpret_cast<double *>(lds_raw + chunk_bytes);
     const bool whole_waves = blockDim.x >= 64;
 

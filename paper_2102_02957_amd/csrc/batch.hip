@@ -43,7 +43,10 @@ struct BatchItem {       // one workgroup of a depth kernel
 constexpr int BATCH_THREADS = 256;
 
 // Section `depth` of every trajectory listed in items: one workgroup per
-// (trajectory, chunk).
+// (trajectory, chunk).  Transpositions move whole amplitudes (a buffer of the
+// chunk's size): trajectory states are small and largely cache-resident, so
+// the two extra barriers of a component-wise transposition cost more here than
+// the extra workgroup per CU it allows would recover.
 template <typename T, int R, int KMAX>
 __global__ void __launch_bounds__(BATCH_THREADS)
 k_batch_step(typename Amp<T>::V *__restrict__ states, const BatchTraj *__restrict__ trajs,
@@ -61,12 +64,12 @@ k_batch_step(typename Amp<T>::V *__restrict__ states, const BatchTraj *__restric
     const cptr<DevSection> S = (cptr<DevSection>)secs_g + (tr.sec_begin + depth);
     const bool active = tid < (1u << (S->c - R));
     if (depth + 1 == tr.nsec) {
-        const double nrm = run_chunk_norm<T, R, KMAX>(st, S, (cptr<DevPhase>)phases_g,
+        const double nrm = run_chunk_norm<T, R, KMAX, false>(st, S, (cptr<DevPhase>)phases_g,
                                                       (cptr<DevOp>)ops_g, (cptr<V>)mats_g, nullptr,
                                                       it.chunk, lds, s_red, active);
         if (tid == 0) partials[tr.part_off + it.chunk] = nrm;
     } else {
-        run_chunk<T, R, KMAX>(st, S, (cptr<DevPhase>)phases_g, (cptr<DevOp>)ops_g,
+        run_chunk<T, R, KMAX, false, false>(st, S, (cptr<DevPhase>)phases_g, (cptr<DevOp>)ops_g,
                               (cptr<V>)mats_g, nullptr, it.chunk, lds, active);
     }
 }
@@ -230,7 +233,7 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
             d.phase_begin += ph0;
             d.phase_end += ph0;
             secs.push_back(d);
-            if (d.phase_end - d.phase_begin > 1) lds = std::max(lds, transpose_lds_bytes(d.c));
+            if (d.phase_end - d.phase_begin > 1) lds = std::max(lds, (size_t(1) << d.c) * es);
         }
         for (const DevPhase &p : P.dphase) {
             DevPhase q = p;

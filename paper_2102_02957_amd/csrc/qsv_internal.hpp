@@ -22,10 +22,10 @@ namespace qsv {
 
 using cd = std::complex<double>;
 
-// LDS transpositions move 8-byte elements (a complex128 amplitude in two
-// passes), so a section's transposition buffer is 2^c * 8 bytes for either type.
-constexpr unsigned TRANSPOSE_LDS_ELEM = 8;
-inline size_t transpose_lds_bytes(int c) { return (size_t(1) << c) * TRANSPOSE_LDS_ELEM; }
+// LDS transpositions move one real component at a time (real parts, then
+// imaginary parts), so a section's transposition buffer holds 2^c components:
+// half the chunk's bytes.
+inline size_t transpose_lds_bytes(int c, size_t amp_bytes) { return (size_t(1) << c) * (amp_bytes / 2); }
 
 // ---- device-side plan records (plain data, copied to the GPU) -------------
 

@@ -222,7 +222,7 @@ qsv_status check_state(qsv_ctx *ctx, const void *state, int n) {
 size_t section_lds(const Plan &P, int s) {
     const DevSection &S = P.dsec[s];
     if (S.phase_end - S.phase_begin <= 1) return 0;
-    return transpose_lds_bytes(S.c);
+    return transpose_lds_bytes(S.c, amp_bytes(P.dtype));
 }
 
 qsv_status ensure_ptab(qsv_ctx *ctx, size_t bytes) {

@@ -293,31 +293,24 @@ __device__ __forceinline__ uint32_t lds_xad(uint32_t t, uint32_t u, uint32_t bas
     asm("v_xad_u32 %0, %1, %2, %3" : "=v"(r) : "v"(t), "s"(u), "v"(base));
     return r;
 }
-// one 8-byte amplitude to / from an LDS byte address (a single access)
-template <typename V> __device__ __forceinline__ void lds_put(uint32_t addr, const V &v) {
-    using E = decltype(v.x);
-    typedef E __attribute__((ext_vector_type(2))) E2;
-    E2 w;
-    w.x = v.x;
-    w.y = v.y;
-    *(__attribute__((address_space(3))) E2 *)(uintptr_t)addr = w;
+// one LDS element (a real component or a whole amplitude) to / from an LDS
+// byte address: a single access
+template <typename L> __device__ __forceinline__ void lds_put(uint32_t addr, L v) {
+    *(__attribute__((address_space(3))) L *)(uintptr_t)addr = v;
 }
-template <typename V> __device__ __forceinline__ V lds_get(uint32_t addr) {
-    using E = decltype(V{}.x);
-    typedef E __attribute__((ext_vector_type(2))) E2;
-    const E2 w = *(__attribute__((address_space(3))) E2 *)(uintptr_t)addr;
-    V v;
-    v.x = w.x;
-    v.y = w.y;
-    return v;
+template <typename L> __device__ __forceinline__ L lds_get(uint32_t addr) {
+    return *(__attribute__((address_space(3))) L *)(uintptr_t)addr;
 }
 
-// LDS bank swizzle of the index of an 8-byte element: XOR-fold the higher index
-// bits into the bank-selecting low bits (128 B rows).  The map is linear over
-// GF(2), swz(x ^ y) = swz(x) ^ swz(y), so the address of every element is the
-// thread's swizzled part XOR a uniform (scalar) swizzled register part.
-__device__ __forceinline__ uint32_t lds_swizzle(uint32_t j) {
-    return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15u);
+// LDS bank swizzle of the index of an EB-byte element: XOR-fold the higher
+// index bits into the bank-selecting low bits (128 B rows: 8 elements of 16
+// bytes, 16 of 8 or 32 of 4).  The map is linear over GF(2), swz(x ^ y) =
+// swz(x) ^ swz(y), so the address of every element is the thread's swizzled
+// part XOR a uniform (scalar) swizzled register part.
+template <int EB> __device__ __forceinline__ uint32_t lds_swizzle(uint32_t j) {
+    if constexpr (EB == 16) return j ^ (((j >> 3) ^ (j >> 6) ^ (j >> 9) ^ (j >> 12)) & 7u);
+    else if constexpr (EB == 8) return j ^ (((j >> 4) ^ (j >> 8) ^ (j >> 12)) & 15u);
+    else return j ^ (((j >> 5) ^ (j >> 10)) & 31u);
 }
 
 
@@ -382,20 +375,24 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// LDS transposition from position->slot map `from` to map `to`, through a
-// buffer of 2^c 8-byte elements (TRANSPOSE_LDS_ELEM): a complex64 amplitude
-// moves whole, a complex128 amplitude in two passes, real parts then imaginary
-// parts.  Half the LDS of a whole-amplitude buffer lets a third complex128
-// workgroup share a CU at c = 12, which hides more HBM and barrier latency than
-// the two extra barriers cost.  Threads with active == false take part in the
+// LDS transposition from position->slot map `from` to map `to`.  SPLIT: one
+// real component at a time, real parts then imaginary parts, through a buffer
+// of 2^c components (half the chunk's bytes).  Compared with moving whole
+// amplitudes (SPLIT = false, a buffer of the chunk's size) this adds two
+// barriers per transposition and halves the LDS a workgroup holds, which lets
+// three section workgroups share a CU (c = 12 complex128, c = 13 complex64)
+// instead of two: for HBM-resident states the extra one hides more latency
+// than the barriers cost.  Threads with active == false take part in the
 // barriers only.
-template <typename V, int R>
+template <typename V, int R, bool SPLIT = true>
 __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uint8_t> from_tab,
                                                 cptr<uint8_t> to_tab, unsigned tid, int TB,
                                                 bool active) {
     using E = decltype(V{}.x);
-    constexpr bool split = sizeof(V) == 2 * TRANSPOSE_LDS_ELEM;
-    static_assert(split || sizeof(V) == TRANSPOSE_LDS_ELEM, "8- or 16-byte amplitudes");
+    typedef E __attribute__((ext_vector_type(2))) E2;
+    using L = typename std::conditional<SPLIT, E, E2>::type;  // LDS element
+    constexpr int EB = sizeof(L);
+    static_assert(EB == 4 || EB == 8 || EB == 16, "float or double components");
     const Bytes16 from = ld16(from_tab), to = ld16(to_tab);
     uint32_t tw = 0, tr = 0;
     static_for<9>([&](auto B) __attribute__((always_inline)) {
@@ -406,16 +403,15 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
     });
     // byte offsets: thread part (per lane) ^ register part (uniform, one scalar
     // value per register bit, combined per element)
-    constexpr uint32_t EB = TRANSPOSE_LDS_ELEM;
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)lds;
-    const uint32_t tws = lds_swizzle(tw) * EB;
-    const uint32_t trs = lds_swizzle(tr) * EB;
+    const uint32_t tws = lds_swizzle<EB>(tw) * EB;
+    const uint32_t trs = lds_swizzle<EB>(tr) * EB;
     uint32_t sw[R], sr[R];
     static_for<R>([&](auto B) __attribute__((always_inline)) {
-        sw[B.value] = lds_swizzle(1u << from[B.value]) * EB;
-        sr[B.value] = lds_swizzle(1u << to[B.value]) * EB;
+        sw[B.value] = lds_swizzle<EB>(1u << from[B.value]) * EB;
+        sr[B.value] = lds_swizzle<EB>(1u << to[B.value]) * EB;
     });
-    static_for<split ? 2 : 1>([&](auto H) __attribute__((always_inline)) {
+    static_for<SPLIT ? 2 : 1>([&](auto H) __attribute__((always_inline)) {
         lds_barrier();  // the previous pass's reads are done before this pass writes
         if (active) {
             static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
@@ -423,12 +419,14 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
                 static_for<R>([&](auto B) __attribute__((always_inline)) {
                     if constexpr (((I.value >> B.value) & 1) != 0) u ^= sw[B.value];
                 });
-                const uint32_t addr = lds_xad(tws, u, lbase);
-                if constexpr (split)
-                    *(__attribute__((address_space(3))) E *)(uintptr_t)addr =
-                        H.value == 0 ? a[I.value].x : a[I.value].y;
-                else
-                    lds_put<V>(addr, a[I.value]);
+                L w;
+                if constexpr (SPLIT) {
+                    w = H.value == 0 ? a[I.value].x : a[I.value].y;
+                } else {
+                    w.x = a[I.value].x;
+                    w.y = a[I.value].y;
+                }
+                lds_put<L>(lds_xad(tws, u, lbase), w);
             });
         }
         lds_barrier();
@@ -438,13 +436,14 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
                 static_for<R>([&](auto B) __attribute__((always_inline)) {
                     if constexpr (((I.value >> B.value) & 1) != 0) u ^= sr[B.value];
                 });
-                const uint32_t addr = lds_xad(trs, u, lbase);
-                if constexpr (split) {
-                    const E v = *(__attribute__((address_space(3))) E *)(uintptr_t)addr;
-                    if constexpr (H.value == 0) a[I.value].x = v;
-                    else a[I.value].y = v;
+                const L v = lds_get<L>(lds_xad(trs, u, lbase));
+                if constexpr (!SPLIT) {
+                    a[I.value].x = v.x;
+                    a[I.value].y = v.y;
+                } else if constexpr (H.value == 0) {
+                    a[I.value].x = v;
                 } else {
-                    a[I.value] = lds_get<V>(addr);
+                    a[I.value].y = v;
                 }
             });
         }
@@ -559,7 +558,7 @@ __device__ __forceinline__ uint64_t chunk_base(cptr<DevSection> S, uint64_t chun
 }
 
 // All phases of one section on the registers of one chunk (no HBM traffic).
-template <typename T, int R, int KMAX, bool DENSE_ONLY = false>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool SPLIT = true>
 __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cptr<DevPhase> ph,
                                              int nph, cptr<DevOp> ops,
                                              cptr<typename Amp<T>::V> mats,
@@ -572,12 +571,12 @@ __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cp
         const cptr<DevPhase> P = ph + p;
         chunk_ops<T, R, KMAX, DENSE_ONLY>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
         if (p + 1 < nph)
-            chunk_transpose<V, R>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
+            chunk_transpose<V, R, SPLIT>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
     }
 }
 
 // One chunk of one section, forward: gather, phases, scatter.
-template <typename T, int R, int KMAX, bool DENSE_ONLY = false>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool SPLIT = true>
 __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
                                           cptr<DevSection> S, cptr<DevPhase> phases,
                                           cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
@@ -591,7 +590,7 @@ __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
     if (active) chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
-    chunk_phases<T, R, KMAX, DENSE_ONLY>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
+    chunk_phases<T, R, KMAX, DENSE_ONLY, SPLIT>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
     if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
     if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
 }
@@ -608,7 +607,7 @@ template <typename V, int R> __device__ __forceinline__ double reg_norm2(const V
 // Same as run_chunk, and also returns (in thread 0) the chunk's FP64 sum of
 // |a|^2 after the section, reduced in a fixed order through `red` (blockDim.x
 // doubles of LDS).
-template <typename T, int R, int KMAX>
+template <typename T, int R, int KMAX, bool SPLIT = true>
 __device__ __forceinline__ double run_chunk_norm(typename Amp<T>::V *__restrict__ st,
                                                  cptr<DevSection> S, cptr<DevPhase> phases,
                                                  cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
@@ -622,7 +621,7 @@ __device__ __forceinline__ double run_chunk_norm(typename Amp<T>::V *__restrict_
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
     if (active) chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
-    chunk_phases<T, R, KMAX>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
+    chunk_phases<T, R, KMAX, false, SPLIT>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
     if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
     if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
     red[tid] = active ? reg_norm2<V, R>(a) : 0.0;
