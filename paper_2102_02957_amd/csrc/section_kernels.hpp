@@ -25,7 +25,8 @@ namespace qsv {
 using namespace sec;
 
 // KMAX: widest dense op the kernel instance carries code for (register pressure
-// of the whole kernel follows the widest case, so narrow plans use KMAX = 2).
+// of the whole kernel follows the widest case, so narrow plans use KMAX = 2;
+// dense-only sections of 3-qubit fused ops have their own KMAX = 3 instance).
 // Up to 512 threads per workgroup for R <= 4 (chunk_bits - R <= 9), 256 for R = 5
 // (whose amplitude registers need the larger per-thread register budget).
 template <int R> constexpr int section_max_threads() { return R <= 4 ? 512 : 256; }
@@ -78,6 +79,7 @@ inline hipError_t launch_section_dt(int r, int kmax, bool dense_only, void *stat
         case 2: QSV_SEC(2, 2, false);
         case 3: if (wide) QSV_SEC(3, 3, false); else QSV_SEC(3, 2, false);
         case 4:
+            if (kmax == 3 && dense_only) QSV_SEC(4, 3, true);
             if (wide) QSV_SEC(4, 4, false);
             else if (dense_only) QSV_SEC(4, 2, true);
             else QSV_SEC(4, 2, false);
