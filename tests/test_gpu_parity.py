@@ -156,6 +156,20 @@ def test_qv_512_thread_sections(torch, ctxs, dt):
 
 
 @pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_qv_fusion3_dense_only(torch, ctxs, dt):
+    """fusion_max_qubits 3 on Quantum Volume: SU(4) pairs sharing a qubit fuse
+    into 3-qubit dense ops, so the dense-only sections run on the r = 4,
+    KMAX = 3 dense-only kernel instance."""
+    n = 20
+    gates = W.quantum_volume(n, n, 3)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, chunk_bits=12, register_bits=4,
+                        pinned_low_bits=3, fusion_max_qubits=3)
+    s = plan.stats()
+    assert s["n_device_ops"] < s["n_gates"]
+    assert_close(got, oracle.apply_circuit(n, gates), dt, "qv20 fusion 3")
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
 def test_io_phases_option(torch, ctxs, dt):
     """io_phases = 1: sections gather/scatter through an extra op-free phase
     in the coalesced map (applies when the state has >= 2^8 chunks)."""
