@@ -22,9 +22,10 @@ namespace qsv {
 
 using cd = std::complex<double>;
 
-// LDS transpositions move one real component at a time (real parts, then
-// imaginary parts), so a section's transposition buffer holds 2^c components:
-// half the chunk's bytes.
+// The section and adjoint kernels transpose one real component at a time
+// (real parts, then imaginary parts), so their transposition buffer holds 2^c
+// components: half the chunk's bytes.  (The batch kernel moves whole
+// amplitudes and sizes its buffer itself.)
 inline size_t transpose_lds_bytes(int c, size_t amp_bytes) { return (size_t(1) << c) * (amp_bytes / 2); }
 
 // ---- device-side plan records (plain data, copied to the GPU) -------------
