@@ -25,6 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# MI355X vector peaks (256 CUs x 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s,
+# of which single-issue (non-packed) FP32 reaches half
+ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "section_kernel_qv33_c128_traffic.json")
 
 
@@ -70,10 +73,26 @@ def blas_threads():
         return 1
 
 
+def one_thread():
+    """Context that limits BLAS/OpenMP pools to one thread (the oracle's
+    elementwise NumPy work is single-threaded anyway), so `cores` is 1."""
+    try:
+        from threadpoolctl import threadpool_limits
+        return threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        import contextlib
+        return contextlib.nullcontext()
+
+
 def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
-    """The oracle as it stands, on a bounded sample of the same workload:
-    a 24-qubit Quantum-Volume circuit, gates applied until ~15 s have passed;
-    the per-gate-per-amplitude time is scaled to the 33-qubit circuit."""
+    """The oracle as it stands, on one host core, on a bounded sample of the
+    same workload: a 24-qubit Quantum-Volume circuit, gates applied until ~15 s
+    have passed; the per-gate-per-amplitude time is scaled to the full circuit."""
+    with one_thread():
+        return _cpu_baseline(n_target, gates_target, blocked_bytes, seed)
+
+
+def _cpu_baseline(n_target, gates_target, blocked_bytes, seed):
     import numpy as np
     import oracle
     from paper_2102_02957_amd import workloads as W
@@ -95,6 +114,7 @@ def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
         "value": blocked_bytes / t_full / 1e9,
         "unit": "GB/s",
         "cores": int(threads),
+        "host_cores": len(os.sched_getaffinity(0)),
         "kind": "oracle",
         "sample": "NumPy oracle, %d of %d SU(4) gates of a %d-qubit QV circuit in %.1f s; "
                   "time per gate per amplitude scaled x%d gates x2^%d amplitudes "
@@ -103,6 +123,33 @@ def cpu_baseline(n_target, gates_target, blocked_bytes, seed):
         "cpu": platform.processor() or platform.machine(),
         "affinity_cores": len(os.sched_getaffinity(0)),
     }
+
+
+def roofline(st, dt, B, steps, pass_bytes, achieved_gbs, avg_launch_ms, sec_ms, launches, traffic):
+    """The section kernel against both of its rooflines.  Per launch it moves one
+    pass (2 * 2^n * es bytes) and performs section_flops / sections FP operations;
+    the binding roofline is the one whose floor (work / peak) is longer."""
+    fdt = "f64" if dt == B.QSV_C128 else "f32"
+    alu_peak = ALU_PEAK_TFLOPS[fdt]
+    flops_launch = st["section_flops"] / max(1, st["n_sections"])
+    t_alu = flops_launch / (alu_peak * 1e12)
+    t_hbm = pass_bytes / (HBM_PEAK_GBS * 1e9)
+    alu_tflops = st["section_flops"] * steps / (sec_ms * 1e-3) / 1e12
+    hbm = {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "floor_ms": round(t_hbm * 1e3, 2),
+           "traffic": traffic}
+    alu = {"achieved": round(alu_tflops, 2), "peak": alu_peak, "unit": "TFLOP/s",
+           "frac": round(alu_tflops / alu_peak, 4), "floor_ms": round(t_alu * 1e3, 2),
+           "dtype": fdt}
+    main = alu if t_alu > t_hbm else hbm
+    out = {"bound": "alu" if t_alu > t_hbm else "hbm"}
+    out.update({k: main[k] for k in ("achieved", "peak", "unit", "frac")})
+    out["traffic"] = traffic
+    out.update({"kernel": "k_section<%s, %d, ...> (one launch per section)"
+                          % ("double" if dt == B.QSV_C128 else "float", st["register_bits"]),
+                "avg_launch_ms": round(avg_launch_ms, 3), "launches": launches,
+                "hbm": hbm, "alu": alu})
+    return out
 
 
 def timed_calls(torch, fn, steps, warmup):
@@ -166,16 +213,17 @@ def bench_trajectories(args, torch, B, W):
         sample = sorted(range(len(trajs)), key=lambda b: trajs[b][0])
         t0 = time.perf_counter()
         work_done, k = 0.0, 0
-        while k < len(sample) and time.perf_counter() - t0 < 10.0:
-            n, g = trajs[sample[k]]
-            oracle.apply_circuit(n, g)
-            work_done += len(g) * float(1 << n)
-            k += 1
+        with one_thread():
+            while k < len(sample) and time.perf_counter() - t0 < 10.0:
+                n, g = trajs[sample[k]]
+                oracle.apply_circuit(n, g)
+                work_done += len(g) * float(1 << n)
+                k += 1
         dt_cpu = time.perf_counter() - t0
         work_all = sum(len(g) * float(1 << n) for n, g in trajs)
         t_full = dt_cpu * work_all / work_done
         rec["cpu_baseline"] = {"value": round(len(trajs) / t_full, 3), "unit": "trajectories/s",
-                               "cores": blas_threads(), "kind": "oracle",
+                               "cores": 1, "kind": "oracle", "host_cores": len(os.sched_getaffinity(0)),
                                "sample": "%d smallest trajectories in %.1f s, scaled by gates x amplitudes "
                                          "to all 512 (extrapolated %.0f s)" % (k, dt_cpu, t_full)}
     print(json.dumps(rec), flush=True)
@@ -238,13 +286,14 @@ def bench_adjoint(args, torch, B, W):
         ts = [(1.0, (1 << i) | (1 << ((i + 1) % ns))) for i in range(ns)]
         t0 = time.perf_counter()
         reps = 0
-        while reps == 0 or time.perf_counter() - t0 < 10.0:
-            oracle.adjoint_gradient(ns, tm, th, ts)
-            reps += 1
+        with one_thread():
+            while reps == 0 or time.perf_counter() - t0 < 10.0:
+                oracle.adjoint_gradient(ns, tm, th, ts)
+                reps += 1
         dt_cpu = (time.perf_counter() - t0) / reps
         t_one = dt_cpu * float(1 << (n - ns))
         rec["cpu_baseline"] = {"value": round(1.0 / t_one, 5), "unit": "gradients/s",
-                               "cores": blas_threads(), "kind": "oracle",
+                               "cores": 1, "kind": "oracle", "host_cores": len(os.sched_getaffinity(0)),
                                "sample": "oracle adjoint gradient of a 14-qubit 40-layer ansatz, %d "
                                          "evaluation(s) in %.1f s, scaled x2^6 amplitudes "
                                          "(extrapolated %.1f s per 20-qubit gradient)"
@@ -367,7 +416,8 @@ def main():
             traffic = prof.get("bytes_per_launch")
 
     rec = {
-        "metric": "blocked gate-apply GB/s (% HBM peak) vs per-gate path, 33q c128 at 1-F<1e-12",
+        "metric": "blocked gate-apply GB/s (%% HBM peak) vs per-gate path, %dq %s at 1-F<%g"
+                  % (n, args.dtype, 1e-12 if dt == B.QSV_C128 else 1e-5),
         "value": round(value, 2),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -400,19 +450,8 @@ def main():
         "copy_kernel_gbs": None if copy_gbs is None else round(copy_gbs, 1),
         "final_norm": nrm,
         "parity": parity,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_section<%s, %d, ...> (one launch per section)"
-                      % ("double" if dt == B.QSV_C128 else "float", st["register_bits"]),
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "avg_launch_ms": round(avg_launch_ms, 3),
-            "launches": sec_launches,
-            "alu_tflops": round(st["section_flops"] * args.steps / (sec_ms * 1e-3) / 1e12, 2),
-        },
+        "roofline": roofline(st, dt, B, args.steps, pass_bytes, achieved, avg_launch_ms,
+                             sec_ms, sec_launches, traffic),
     }
     if not args.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(n, gates, step_bytes, args.seed)

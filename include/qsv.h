@@ -9,7 +9,7 @@
  *
  *   Blocked mode follows the paper's cache blocking (Sec. IV): the circuit is
  *   transpiled into sections (begin_blocking ... end_blocking) each of which
- *   acts only on the 2^c amplitudes of a chunk (Sec. III-B, IV-C), with
+ *   acts only on the 2^c amplitudes of a chunk (Sec. II-B, IV-C), with
  *   chunk_swap operations between sections choosing which qubits are local.
  *   On one GPU the chunk is staged in on-chip memory (registers + LDS) instead
  *   of GPU memory, so every section costs one read and one write of the state
@@ -21,8 +21,19 @@
  *     interleaved (re, im): float pairs for QSV_C64, double pairs for
  *     QSV_C128, 256-byte aligned.  The library never frees or reallocates it.
  *   - All device work is asynchronous on the caller's HIP stream `stream`
- *     (hipStream_t passed as void*; NULL = the default stream).  Device faults
+ *     (hipStream_t passed as void*; NULL = the default stream); no call
+ *     synchronises the stream except qsv_timing_read.  Host arrays passed in
+ *     (gates, terms, offsets) are read during the call only.  Device faults
  *     surface at the caller's next synchronisation.
+ *   - A context may be used from several streams and threads.  Calls are
+ *     serialised on the host; the context's device workspaces (parameter
+ *     tables, reduction partials, observable tables) are ordered across streams
+ *     with events, so the device work of two calls on different streams never
+ *     shares them concurrently.  Under HIP graph capture no event is recorded:
+ *     a context used inside a captured graph must not be used from another
+ *     stream while that graph runs, and qsv_reserve must have sized its
+ *     workspaces beforehand (a workspace that would have to grow during
+ *     capture returns QSV_E_STATE).
  *   - Every call returns a qsv_status; nothing throws across the ABI.  A
  *     thread-local message for the last failure is returned by qsv_last_error().
  *   - Arguments are validated eagerly on the host; an invalid call leaves all
@@ -44,7 +55,7 @@ typedef enum {
     QSV_E_NOMEM = -2,       /* a library-owned workspace allocation failed */
     QSV_E_HIP = -3,         /* a HIP runtime call or kernel launch failed */
     QSV_E_UNSUPPORTED = -4, /* valid request this build does not handle */
-    QSV_E_NUMERIC = -5,     /* non-finite or zero norm where one is required */
+    QSV_E_NUMERIC = -5,     /* non-finite angle, matrix entry or observable coefficient */
     QSV_E_STATE = -6        /* call out of order (e.g. destroyed object) */
 } qsv_status;
 
@@ -69,6 +80,7 @@ enum {
 
 #define QSV_MAX_QUBITS 34       /* 2^34 amplitudes: 128 GiB complex64, 256 GiB complex128 */
 #define QSV_MAX_GATE_QUBITS 5
+#define QSV_MAX_TERMS 4096      /* Z-strings per observable */
 
 typedef struct {
     int32_t kind;
@@ -85,7 +97,7 @@ enum { QSV_SWAP_REMAP = 0, QSV_SWAP_MATERIALIZE = 1 };
 enum { QSV_MODE_BLOCKED = 0, QSV_MODE_PER_GATE = 1 };
 
 typedef struct {
-    int32_t chunk_bits;          /* c: qubits per chunk (Sec. III-B "nc"); 0 = default
+    int32_t chunk_bits;          /* c: qubits per chunk (Sec. II-B "nc"); 0 = default
                                     (12 for QSV_C128, 13 for QSV_C64) */
     int32_t pinned_low_bits;     /* L: physical bits 0..L-1 always local (coalescing); -1 = default */
     int32_t fusion_max_qubits;   /* f: fuse consecutive in-section gates up to f qubits; 0/1 = off */
@@ -116,13 +128,17 @@ typedef struct qsv_plan qsv_plan;
  * only.  n in [1, QSV_MAX_QUBITS].  The plan is immutable and may be shared
  * between threads and contexts; destroy it only when no launch using it is in
  * flight.  Errors: QSV_E_INVALID on a bad gate (kind, nq, qubit range,
- * duplicates, missing matrix) or option. */
+ * duplicates, missing matrix) or option; QSV_E_NUMERIC on a non-finite angle or
+ * matrix entry; QSV_E_UNSUPPORTED when the launch grid of a section would exceed
+ * the hardware limits (n - register_bits > 31 or n - chunk_bits > 30). */
 qsv_status qsv_plan_blocks(const qsv_options *opt, qsv_dtype dt, int n,
                            const qsv_gate *g, size_t ng, qsv_plan **plan);
 void qsv_plan_destroy(qsv_plan *plan);
 
 typedef struct {
-    int32_t n, dtype, chunk_bits, register_bits, pinned_low_bits, fusion_max_qubits;
+    int32_t n, dtype, chunk_bits, register_bits, pinned_low_bits;
+    int32_t fusion_max_qubits;   /* fusion width applied: the requested one capped at
+                                    register_bits and at 4 */
     int32_t swap_mode, diag_free;
     int64_t n_gates;             /* gates in the circuit */
     int64_t n_sections;          /* begin_blocking/end_blocking pairs */
@@ -153,12 +169,27 @@ qsv_status qsv_plan_export(const qsv_plan *plan, qsv_op *ops, size_t cap, size_t
 
 typedef struct qsv_ctx qsv_ctx;
 
-/* Bind a context to HIP device `hip_device` for states of type dt.  The
- * context owns small workspaces (uploaded plan tables, reduction partials),
- * grown on demand.  Errors: QSV_E_HIP if the device is absent. */
+/* Bind a context to HIP device `hip_device` for states of type dt: the
+ * memory space that holds the state (Sec. II-B: one memory space per GPU;
+ * Sec. IV-B: the state and its chunks live in the GPU's memory).  The context
+ * owns small workspaces (uploaded plan tables, reduction partials, parameter
+ * and observable tables), grown on demand or sized up front by qsv_reserve.
+ * Options are per plan (qsv_plan_blocks), not per context.
+ * Errors: QSV_E_HIP if no device is present, QSV_E_INVALID for a bad device
+ * index or dtype. */
 qsv_status qsv_create(qsv_ctx **ctx, int hip_device, qsv_dtype dt);
 void qsv_destroy(qsv_ctx *ctx);
 const char *qsv_last_error(void);
+
+/* Size every context workspace that the calls below need for `plan` (or, with
+ * plan == NULL, for reductions over states of n qubits) and `batch` states,
+ * and upload the plan's device tables.  After it, qsv_apply_circuit,
+ * qsv_apply_sections, qsv_apply_params, qsv_norm, qsv_overlap, qsv_expval,
+ * qsv_normalize and qsv_adjoint_grad with that plan (n, batch at most the
+ * reserved ones, at most QSV_MAX_TERMS terms) allocate nothing and only
+ * enqueue kernels, so they may be captured into a HIP graph.  Must not be
+ * called during capture (QSV_E_STATE). */
+qsv_status qsv_reserve(qsv_ctx *ctx, const qsv_plan *plan, int n, int batch, void *stream);
 
 /* state <- |basis> (Sec. IV-C: only one amplitude is 1, the rest 0). */
 qsv_status qsv_init_basis(qsv_ctx *ctx, void *state, int n, uint64_t basis, void *stream);
@@ -193,7 +224,10 @@ qsv_status qsv_norm(qsv_ctx *ctx, const void *state, int n, double *out_dev, voi
 /* out_dev[0..3] = Re<a|b>, Im<a|b>, <a|a>, <b|b> */
 qsv_status qsv_overlap(qsv_ctx *ctx, const void *a, const void *b, int n, double *out_dev,
                        void *stream);
-/* out_dev[0] = sum_x |a_x|^2 sum_t coeff_t (-1)^popcount(x & zmask_t)  (terms: host array) */
+/* out_dev[0] = sum_x |a_x|^2 sum_t coeff_t (-1)^popcount(x & zmask_t).  terms: host
+ * array of 1..QSV_MAX_TERMS entries, read during the call (it travels to the device in
+ * kernel arguments; the call does not synchronise).  QSV_E_NUMERIC for a non-finite
+ * coefficient. */
 qsv_status qsv_expval(qsv_ctx *ctx, const void *state, int n, const qsv_zterm *terms,
                       size_t n_terms, double *out_dev, void *stream);
 /* Divide the state by sqrt(<psi|psi>) (computed in FP64); norm_out_dev[0] = <psi|psi>
@@ -222,7 +256,8 @@ qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm 
 /* ---- batched trajectories ---------------------------------------------- */
 
 /* Run `count` independent circuits (e.g. noisy trajectories with sampled Pauli
- * insertions), each on its own state of n_b qubits stored at states + offsets[b]
+ * insertions: the noisy simulation and repeated shots of Sec. III-A, each run as its
+ * own state), each on its own state of n_b qubits stored at states + offsets[b]
  * amplitudes (offsets: host array; states must not overlap and must start on 256-byte
  * boundaries), in one graph launch: every state is set to |0>; then, for each section
  * depth d, one kernel runs section d of every plan that has one, a workgroup per
@@ -244,7 +279,7 @@ qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *const *plans,
  * `stream`.  *best = index of the fastest candidate; ms_out[k] (host, may be NULL) =
  * mean milliseconds per apply, +inf for candidates that cannot be planned.  Chooses
  * chunk_bits, pinned_low_bits, fusion_max_qubits and register_bits for the caller's
- * own workload (the paper's chunk size nc, Sec. III-B, is a free parameter). */
+ * own workload (the paper's chunk size nc, Sec. II-B, is a free parameter). */
 qsv_status qsv_autotune(qsv_ctx *ctx, qsv_dtype dt, int n, const qsv_gate *g, size_t ng,
                         const qsv_options *cands, int n_cands, void *state, int reps, void *stream,
                         int *best, double *ms_out);

@@ -32,7 +32,7 @@ from .statevector import (zero_state, basis_state, apply_gate, apply_circuit,
                           apply_matrix, apply_1q_pairwise, bind_params)
 from .observables import (norm2, overlap, fidelity, max_abs_diff,
                           zstring_expval, ring_zz_terms, zz_diag_values)
-from .adjoint import (adjoint_gradient, parameter_shift_gradient,
+from .adjoint import (adjoint_gradient, parameter_shift_gradient, parameter_shift_tail,
                       finite_difference_gradient, energy)
 from .plan_exec import run_plan
 from .closed_forms import qft_basis_amplitude, ghz_state
@@ -43,6 +43,6 @@ __all__ = [
     "apply_1q_pairwise", "bind_params",
     "norm2", "overlap", "fidelity", "max_abs_diff", "zstring_expval",
     "ring_zz_terms", "zz_diag_values",
-    "adjoint_gradient", "parameter_shift_gradient", "finite_difference_gradient",
+    "adjoint_gradient", "parameter_shift_gradient", "parameter_shift_tail", "finite_difference_gradient",
     "energy", "run_plan", "qft_basis_amplitude", "ghz_state",
 ]

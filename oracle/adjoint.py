@@ -11,6 +11,11 @@ Three independent routes:
 * ``parameter_shift_gradient`` -- [E(theta_j + pi/2) - E(theta_j - pi/2)] / 2,
   exact for gates exp(-i theta P / 2) with a Pauli P (rx, ry, rz);
 * ``finite_difference_gradient`` -- central differences.
+
+``parameter_shift_tail`` evaluates the same shift rule but applies the gates in
+front of the first gate that a shifted parameter drives only once (that prefix
+state does not depend on the shifted parameters); it makes a few entries at 20
+qubits affordable when the parameters sit near the end of the circuit.
 """
 
 import math
@@ -77,4 +82,28 @@ def finite_difference_gradient(n, gates, theta, terms, h=1e-6, indices=None):
         tm = theta.copy()
         tm[p] -= h
         out[p] = (energy(n, gates, tp, terms) - energy(n, gates, tm, terms)) / (2 * h)
+    return out
+
+
+def parameter_shift_tail(n, gates, theta, terms, indices):
+    """Parameter-shift entries {p: dE/dtheta_p} for p in `indices`, sharing the
+    unshifted prefix state (see the module docstring)."""
+    theta = np.asarray(theta, dtype=np.float64)
+    idx = set(int(p) for p in indices)
+    first = len(gates)
+    for j, g in enumerate(gates):
+        pidx = g[4] if len(g) > 4 else -1
+        if pidx is not None and pidx >= 0 and pidx in idx:
+            first = j
+            break
+    prefix = apply_circuit(n, bind_params(gates[:first], theta))
+    out = {}
+    for p in sorted(idx):
+        es = []
+        for sgn in (+1, -1):
+            t = theta.copy()
+            t[p] += sgn * math.pi / 2
+            psi = apply_circuit(n, bind_params(gates[first:], t), prefix.copy())
+            es.append(zstring_expval(psi, n, terms))
+        out[p] = 0.5 * (es[0] - es[1])
     return out

@@ -72,6 +72,7 @@ EXPORTED = [
     "qsv_apply_circuit", "qsv_apply_sections", "qsv_apply_params", "qsv_norm", "qsv_overlap",
     "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
     "qsv_timing_enable", "qsv_timing_read", "qsv_autotune", "qsv_autotune_batch",
+    "qsv_reserve",
 ]
 
 _lib = None
@@ -108,6 +109,7 @@ def lib():
         "qsv_copy": (I, [P, P, P, I, P]),
         "qsv_adjoint_grad": (I, [P, P, ctypes.POINTER(ZTerm), SZ, P, I, P, P, P, P, P]),
         "qsv_batch_run": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(U64), P, P, P]),
+        "qsv_reserve": (I, [P, P, I, I, P]),
         "qsv_timing_enable": (I, [P, I]),
         "qsv_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), I]),
         "qsv_autotune": (I, [P, I, I, ctypes.POINTER(Gate), SZ, ctypes.POINTER(Options), I, P, I, P,
@@ -248,11 +250,23 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def _check_state(t, n, batch=1):
+def _check_state(t, n, batch=1, dtype=None):
+    """Host-side checks the C ABI cannot make (it sees pointers, not sizes)."""
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("state must be a contiguous device tensor")
+    if dtype is not None and dtype_of(t) != dtype:
+        raise ValueError("state dtype %s does not match the context's %s"
+                         % (t.dtype, "complex128" if dtype == QSV_C128 else "complex64"))
     if t.numel() != (batch << n):
         raise ValueError("state must hold %d x 2^%d amplitudes" % (batch, n))
+
+
+def _check_f64(t, shape, what):
+    torch = _torch()
+    if (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+            or tuple(t.shape) != tuple(shape)):
+        raise ValueError("%s must be a contiguous float64 device tensor of shape %s"
+                         % (what, tuple(shape)))
 
 
 class Context:
@@ -272,64 +286,74 @@ class Context:
             self._h = None
 
     def init_basis(self, state, n, basis=0, stream=None):
-        _check_state(state, n)
+        _check_state(state, n, dtype=self.dtype)
         _check(lib().qsv_init_basis(self._h, _ptr(state), n, int(basis), _stream(stream)))
 
     def apply(self, plan, state, mode=QSV_MODE_BLOCKED, stream=None):
-        _check_state(state, plan.n)
+        _check_state(state, plan.n, dtype=self.dtype)
         _check(lib().qsv_apply_circuit(self._h, plan.handle, _ptr(state), plan.n, int(mode),
                                        _stream(stream)))
 
     def apply_sections(self, plan, state, s0, s1, stream=None):
-        _check_state(state, plan.n)
+        _check_state(state, plan.n, dtype=self.dtype)
         _check(lib().qsv_apply_sections(self._h, plan.handle, _ptr(state), plan.n, int(s0),
                                         int(s1), _stream(stream)))
 
+    def reserve(self, plan=None, n=None, batch=1, stream=None):
+        """qsv_reserve: size the workspaces (and upload the plan) so that later
+        calls allocate nothing and can be captured into a graph."""
+        n = plan.n if plan is not None else int(n)
+        _check(lib().qsv_reserve(self._h, plan.handle if plan is not None else None, n,
+                                 int(batch), _stream(stream)))
+
     def apply_params(self, plan, states, params, stream=None):
-        batch = params.shape[0]
-        _check_state(states, plan.n, batch)
-        if params.dtype != _torch().float64 or not params.is_cuda or not params.is_contiguous():
-            raise ValueError("params must be a contiguous float64 device tensor")
+        batch = params.shape[0] if params.dim() == 2 else -1
+        _check_f64(params, (batch, plan.stats()["n_params"]), "params")
+        _check_state(states, plan.n, batch, dtype=self.dtype)
         _check(lib().qsv_apply_params(self._h, plan.handle, _ptr(states), plan.n, int(batch),
                                       _ptr(params), _stream(stream)))
 
     def norm(self, state, n, out=None, stream=None):
         torch = _torch()
-        _check_state(state, n)
+        _check_state(state, n, dtype=self.dtype)
         out = torch.empty(1, dtype=torch.float64, device=state.device) if out is None else out
+        _check_f64(out, (1,), "out")
         _check(lib().qsv_norm(self._h, _ptr(state), n, _ptr(out), _stream(stream)))
         return out
 
     def overlap(self, a, b, n, out=None, stream=None):
         torch = _torch()
-        _check_state(a, n)
-        _check_state(b, n)
+        _check_state(a, n, dtype=self.dtype)
+        _check_state(b, n, dtype=self.dtype)
         out = torch.empty(4, dtype=torch.float64, device=a.device) if out is None else out
+        _check_f64(out, (4,), "out")
         _check(lib().qsv_overlap(self._h, _ptr(a), _ptr(b), n, _ptr(out), _stream(stream)))
         return out
 
     def expval(self, state, n, terms, out=None, stream=None):
         torch = _torch()
-        _check_state(state, n)
+        _check_state(state, n, dtype=self.dtype)
         arr = (ZTerm * len(terms))()
         for i, (c, m) in enumerate(terms):
             arr[i].coeff = float(c)
             arr[i].zmask = int(m)
         out = torch.empty(1, dtype=torch.float64, device=state.device) if out is None else out
+        _check_f64(out, (1,), "out")
         _check(lib().qsv_expval(self._h, _ptr(state), n, arr, len(terms), _ptr(out),
                                 _stream(stream)))
         return out
 
     def normalize(self, state, n, out=None, stream=None):
         torch = _torch()
-        _check_state(state, n)
+        _check_state(state, n, dtype=self.dtype)
         out = torch.empty(1, dtype=torch.float64, device=state.device) if out is None else out
+        _check_f64(out, (1,), "out")
         _check(lib().qsv_normalize(self._h, _ptr(state), n, _ptr(out), _stream(stream)))
         return out
 
     def copy(self, dst, src, n, stream=None):
-        _check_state(dst, n)
-        _check_state(src, n)
+        _check_state(dst, n, dtype=self.dtype)
+        _check_state(src, n, dtype=self.dtype)
         _check(lib().qsv_copy(self._h, _ptr(dst), _ptr(src), n, _stream(stream)))
 
     def timing(self, enable):
@@ -350,12 +374,17 @@ def _batch_run(self, plans, offsets, states, norms=None, stream=None):
     count = len(plans)
     if not states.is_cuda or not states.is_contiguous():
         raise ValueError("states must be a contiguous device tensor")
+    if dtype_of(states) != self.dtype:
+        raise ValueError("states dtype does not match the context")
+    if len(offsets) != count:
+        raise ValueError("one offset per plan")
     for p, o in zip(plans, offsets):
         if o + (1 << p.n) > states.numel():
             raise ValueError("state of a plan runs past the buffer")
     arr = (ctypes.c_void_p * count)(*[p.handle.value for p in plans])
     offs = (ctypes.c_uint64 * count)(*[int(o) for o in offsets])
     norms = torch.empty(count, dtype=torch.float64, device=states.device) if norms is None else norms
+    _check_f64(norms, (count,), "norms")
     _check(lib().qsv_batch_run(self._h, count, arr, offs, _ptr(states), _ptr(norms), _stream(stream)))
     return norms
 
@@ -363,18 +392,19 @@ def _batch_run(self, plans, offsets, states, norms=None, stream=None):
 def _adjoint_grad(self, plan, terms, params, psi, lam, energy=None, grad=None, stream=None):
     """qsv_adjoint_grad: energies [B] and gradients [B, P] of <psi|H|psi>."""
     torch = _torch()
-    batch = params.shape[0]
-    _check_state(psi, plan.n, batch)
-    _check_state(lam, plan.n, batch)
-    if params.dtype != torch.float64 or not params.is_cuda or not params.is_contiguous():
-        raise ValueError("params must be a contiguous float64 device tensor")
+    batch = params.shape[0] if params.dim() == 2 else -1
+    nparams = plan.stats()["n_params"]
+    _check_f64(params, (batch, nparams), "params")
+    _check_state(psi, plan.n, batch, dtype=self.dtype)
+    _check_state(lam, plan.n, batch, dtype=self.dtype)
     arr = (ZTerm * len(terms))()
     for i, (c, m) in enumerate(terms):
         arr[i].coeff = float(c)
         arr[i].zmask = int(m)
-    nparams = plan.stats()["n_params"]
     energy = torch.empty(batch, dtype=torch.float64, device=psi.device) if energy is None else energy
     grad = torch.empty(batch, max(1, nparams), dtype=torch.float64, device=psi.device) if grad is None else grad
+    _check_f64(energy, (batch,), "energy")
+    _check_f64(grad, (batch, max(1, nparams)), "grad")
     _check(lib().qsv_adjoint_grad(self._h, plan.handle, arr, len(terms), _ptr(params), int(batch),
                                   _ptr(psi), _ptr(lam), _ptr(energy), _ptr(grad), _stream(stream)))
     return energy, grad[:, :nparams]

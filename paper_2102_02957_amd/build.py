@@ -1,7 +1,7 @@
 """Build libqsv.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_2102_02957_amd.build  (or build() from Python).
-The library is always rebuilt; sources are compiled in parallel.
+Usage: python -m paper_2102_02957_amd.build [--incremental]  (or build() from Python).
+By default every source is recompiled; sources are compiled in parallel.
 """
 
 import concurrent.futures
@@ -30,9 +30,22 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
           "-mllvm", "-simplifycfg-sink-common=false"]
 
 
-def _compile(src):
+def _stale(obj, src_path):
+    """Object older than its source or than any header (headers are not tracked
+    per source: a header change rebuilds everything)."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    heads = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+    heads += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE)]
+    return any(os.path.getmtime(f) > t for f in [src_path] + heads)
+
+
+def _compile(src, incremental=False):
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, src + ".o")
+    if incremental and not _stale(obj, path):
+        return obj, ""
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip"] + DEVICE + COMMON + ["-c", path, "-o", obj]
     else:
@@ -44,10 +57,12 @@ def _compile(src):
     return obj, msg
 
 
-def build(verbose=False):
+def build(verbose=False, incremental=False):
+    """Compile every source (incremental=True: only sources whose object is
+    older than the source or any header) and link libqsv.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        results = list(ex.map(_compile, SOURCES))
+        results = list(ex.map(lambda f: _compile(f, incremental), SOURCES))
     for obj, msg in results:
         if verbose and msg.strip():
             print(msg)
@@ -61,4 +76,4 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

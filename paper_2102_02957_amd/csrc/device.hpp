@@ -58,6 +58,8 @@ hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, i
 hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,
                                 hipStream_t s);
 int reduce_blocks(int n);
+// copy host Z-string terms to a device table (by value through kernel arguments)
+hipError_t launch_store_terms(const qsv_zterm *host, size_t nt, qsv_zterm *dev, hipStream_t s);
 
 // adjoint.hip
 hipError_t launch_adjoint_section(qsv_dtype dt, int r, void *psi, void *lam, int n, int batch,

@@ -1,5 +1,7 @@
 // State initialisation, copies, bit-swap permutation passes and the FP64
 // reductions (norm, overlap, diagonal Z-string expectation, renormalisation).
+#include <algorithm>
+
 #include "device.hpp"
 
 namespace qsv {
@@ -270,6 +272,35 @@ hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, i
     if (dt == QSV_C128)
         return reduce_t<Cplx<double>>(kind, a, b, n, batch, terms_dev, n_terms, partials, nblk, out, s);
     return reduce_t<Cplx<float>>(kind, a, b, n, batch, terms_dev, n_terms, partials, nblk, out, s);
+}
+
+// Observable upload without a host staging buffer: up to TERMS_PER_LAUNCH
+// terms travel by value in the kernel's argument block, so the host array may
+// be released as soon as the call returns and the copy needs no
+// synchronisation (and may sit in a captured graph).
+constexpr int TERMS_PER_LAUNCH = 128;
+struct TermBlock {
+    qsv_zterm t[TERMS_PER_LAUNCH];
+    int count;
+};
+static_assert(sizeof(TermBlock) <= 4096, "kernel argument block");
+
+__global__ void __launch_bounds__(TERMS_PER_LAUNCH)
+k_store_terms(TermBlock blk, qsv_zterm *__restrict__ dst) {
+    const int i = threadIdx.x;
+    if (i < blk.count) dst[i] = blk.t[i];
+}
+
+hipError_t launch_store_terms(const qsv_zterm *host, size_t nt, qsv_zterm *dev, hipStream_t s) {
+    for (size_t off = 0; off < nt; off += TERMS_PER_LAUNCH) {
+        TermBlock blk;
+        blk.count = (int)std::min<size_t>(TERMS_PER_LAUNCH, nt - off);
+        for (int i = 0; i < blk.count; ++i) blk.t[i] = host[off + i];
+        hipLaunchKernelGGL(k_store_terms, dim3(1), dim3(TERMS_PER_LAUNCH), 0, s, blk, dev + off);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,

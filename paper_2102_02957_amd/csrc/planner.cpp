@@ -204,7 +204,7 @@ int rollout_sections(const Blocker &B, std::vector<int> rem, uint64_t start, int
 
 // ---------------------------------------------------------------------------
 
-static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<GateRec> &out,
+static qsv_status validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<GateRec> &out,
                                int64_t &n_params, std::string &err) {
     out.clear();
     out.reserve(ng);
@@ -216,28 +216,28 @@ static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<
         int nq = 0;
         if (!gate_arity(s.kind, nq)) {
             err = "gate " + std::to_string(i) + ": unknown kind " + std::to_string(s.kind);
-            return false;
+            return QSV_E_INVALID;
         }
         if (nq < 0) {
             if (s.nq < 1 || s.nq > QSV_MAX_GATE_QUBITS) {
                 err = "gate " + std::to_string(i) + ": unitary arity must be 1..5";
-                return false;
+                return QSV_E_INVALID;
             }
             nq = s.nq;
         }
         if (s.nq != nq) {
             err = "gate " + std::to_string(i) + ": nq does not match its kind";
-            return false;
+            return QSV_E_INVALID;
         }
         r.nq = nq;
         for (int j = 0; j < nq; ++j) {
             if (s.q[j] < 0 || s.q[j] >= n) {
                 err = "gate " + std::to_string(i) + ": qubit out of range";
-                return false;
+                return QSV_E_INVALID;
             }
             if (r.qmask & bit(s.q[j])) {
                 err = "gate " + std::to_string(i) + ": repeated qubit";
-                return false;
+                return QSV_E_INVALID;
             }
             r.q[j] = s.q[j];
             r.qmask |= bit(s.q[j]);
@@ -245,13 +245,13 @@ static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<
         for (int j = 0; j < 3; ++j) r.p[j] = s.p[j];
         if (!std::isfinite(r.p[0]) || !std::isfinite(r.p[1]) || !std::isfinite(r.p[2])) {
             err = "gate " + std::to_string(i) + ": non-finite angle";
-            return false;
+            return QSV_E_NUMERIC;
         }
         r.param = s.param;
         if (s.param >= 0) {
             if (s.kind != QSV_RX && s.kind != QSV_RY && s.kind != QSV_RZ && s.kind != QSV_P) {
                 err = "gate " + std::to_string(i) + ": only rx/ry/rz/p take a bound parameter";
-                return false;
+                return QSV_E_INVALID;
             }
             n_params = std::max<int64_t>(n_params, (int64_t)s.param + 1);
         }
@@ -260,7 +260,7 @@ static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<
         if (s.kind == QSV_UNITARY) {
             if (!s.m) {
                 err = "gate " + std::to_string(i) + ": unitary without matrix";
-                return false;
+                return QSV_E_INVALID;
             }
             size_t d = size_t(1) << nq;
             r.m.resize(d * d);
@@ -268,7 +268,7 @@ static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<
                 r.m[e] = cd(s.m[2 * e], s.m[2 * e + 1]);
                 if (!std::isfinite(s.m[2 * e]) || !std::isfinite(s.m[2 * e + 1])) {
                     err = "gate " + std::to_string(i) + ": non-finite matrix entry";
-                    return false;
+                    return QSV_E_NUMERIC;
                 }
             }
             bool diag = true;
@@ -284,7 +284,7 @@ static bool validate_and_build(int n, const qsv_gate *g, size_t ng, std::vector<
         }
         out.push_back(std::move(r));
     }
-    return true;
+    return QSV_OK;
 }
 
 // Permute a k-qubit matrix from gate order (local bit j = gate qubit j) into the
@@ -763,7 +763,7 @@ static void lower_section(Plan &P, int si) {
             }
             pops.push_back(std::move(o));
         }
-        int f = std::min(P.opt.fusion_max_qubits, std::min(R, 4));
+        int f = std::min(P.fusion_eff, R);
         std::vector<POp> fused = fuse(pops, f);
         for (POp &o : fused) {
             if (o.op.type == OP_DENSE || o.op.type == OP_DIAG) {
@@ -935,7 +935,10 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     P = Plan();
     P.n = n;
     P.dtype = dt;
-    if (!validate_and_build(n, g, ng, P.gates, P.n_params, err)) return QSV_E_INVALID;
+    {
+        const qsv_status vs = validate_and_build(n, g, ng, P.gates, P.n_params, err);
+        if (vs != QSV_OK) return vs;
+    }
     int maxk = 1;
     for (const GateRec &r : P.gates)
         if (!r.diagonal && !r.is_swap && r.kind != QSV_CX) maxk = std::max(maxk, r.nq);
@@ -951,6 +954,12 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
               "register_bits = 5 (512 / 256 threads per workgroup)";
         return QSV_E_INVALID;
     }
+    if (n - P.r > 31 || n - P.c > 30) {
+        // a section launch has 2^(n - c) workgroups of 2^(c - r) work-items: at
+        // most 2^31 - 1 workgroups and 2^32 - 1 work-items per grid dimension
+        err = "n - register_bits must be <= 31 and n - chunk_bits <= 30 (launch grid limits)";
+        return QSV_E_UNSUPPORTED;
+    }
     int maxlocal = 1;
     for (const GateRec &r : P.gates) maxlocal = std::max(maxlocal, r.nq);
     if (o.pinned_low_bits > P.c - maxlocal) o.pinned_low_bits = std::max(0, P.c - maxlocal);
@@ -958,6 +967,9 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     o.register_bits = P.r;
     o.chunk_bits = P.c;
     P.opt = o;
+    // fused ops run in one thread's registers: at most r qubits, and at most 4
+    // (the widest fused-op kernel instance)
+    P.fusion_eff = o.fusion_max_qubits < 2 ? o.fusion_max_qubits : std::min(o.fusion_max_qubits, std::min(P.r, 4));
 
     block_circuit(P);
     for (size_t s = 0; s < P.sections.size(); ++s) lower_section(P, (int)s);

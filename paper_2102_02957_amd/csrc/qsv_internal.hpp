@@ -138,6 +138,7 @@ struct Plan {
     qsv_options opt{};
     int c = 0, r = 0;
     int kmax = 1;                           // widest dense in-section op (after fusion)
+    int fusion_eff = 0;                     // fusion width actually applied (<= requested)
     std::vector<GateRec> gates;
     std::vector<HostSection> sections;
     std::vector<int> final_perm;                      // logical -> physical after the last section

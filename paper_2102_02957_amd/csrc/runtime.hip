@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <list>
@@ -48,6 +49,19 @@ struct BatchEntry {
     BatchLaunch launch;
 };
 
+// A device workspace owned by a context.  Calls may come from several streams:
+// each use records an event on its stream, and a use from another stream first
+// makes its stream wait for that event, so device work on one workspace never
+// overlaps.  Under graph capture no event is recorded or waited for (a
+// captured context is used from the capturing stream only).
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t last = nullptr;       // recorded after the last use
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+};
+
 struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<hipEvent_t> pool;
@@ -61,12 +75,9 @@ struct qsv_ctx {
     int device = 0;
     qsv_dtype dtype = QSV_C128;
     std::list<qsv::DevPlanBuf> plans;      // most recent first
-    double *partials = nullptr;
-    size_t partials_bytes = 0;
-    void *ptab = nullptr;                  // per-state parameter tables
-    size_t ptab_bytes = 0;
-    qsv_zterm *terms = nullptr;
-    size_t terms_cap = 0;
+    qsv::Workspace partials;               // reduction / gradient partials (double)
+    qsv::Workspace ptab;                   // per-state parameter tables
+    qsv::Workspace terms;                  // observable Z-strings (qsv_zterm)
     bool timing = false;
     qsv::Timer timers[2];
     std::list<qsv::BatchEntry> batches;    // prepared batch launches, most recent first
@@ -156,18 +167,68 @@ qsv_status upload_plan(qsv_ctx *ctx, const Plan &P, const DevPlanView **out) {
     return QSV_OK;
 }
 
-qsv_status ensure_partials(qsv_ctx *ctx, size_t bytes) {
-    if (ctx->partials_bytes >= bytes) return QSV_OK;
-    if (ctx->partials) (void)hipFree(ctx->partials);
-    ctx->partials = nullptr;
-    ctx->partials_bytes = 0;
-    hipError_t e = hipMalloc((void **)&ctx->partials, bytes);
-    if (e != hipSuccess) {
-        set_error(std::string("reduction workspace: ") + hipGetErrorString(e));
-        return QSV_E_NOMEM;
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st != hipStreamCaptureStatusNone;
+}
+
+// Grow `w` to at least `bytes` and order stream `s` after the workspace's last
+// user.  Growing frees the old buffer after its last use has completed.
+qsv_status ws_acquire(Workspace &w, size_t bytes, hipStream_t s, const char *what) {
+    const bool cap = capturing(s);
+    if (w.bytes < bytes) {
+        if (cap) {
+            set_error(std::string(what) + ": workspace must grow during graph capture "
+                      "(call qsv_reserve before capturing)");
+            return QSV_E_STATE;
+        }
+        if (w.used && w.last) {
+            hipError_t e = hipEventSynchronize(w.last);
+            if (e != hipSuccess) return hip_fail(e, what);
+        }
+        if (w.ptr) (void)hipFree(w.ptr);
+        w.ptr = nullptr;
+        w.bytes = 0;
+        w.used = false;
+        hipError_t e = hipMalloc(&w.ptr, bytes);
+        if (e != hipSuccess) {
+            w.ptr = nullptr;
+            set_error(std::string(what) + ": " + hipGetErrorString(e));
+            return QSV_E_NOMEM;
+        }
+        w.bytes = bytes;
     }
-    ctx->partials_bytes = bytes;
+    if (!w.last) {
+        if (cap) {
+            set_error(std::string(what) + ": first use of a workspace during graph capture "
+                      "(call qsv_reserve before capturing)");
+            return QSV_E_STATE;
+        }
+        hipError_t e = hipEventCreateWithFlags(&w.last, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
+    if (!cap && w.used && w.last_stream != s) {
+        hipError_t e = hipStreamWaitEvent(s, w.last, 0);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
     return QSV_OK;
+}
+
+// Mark the end of a use of `w` on stream `s` (after the launches that read or write it).
+qsv_status ws_release(Workspace &w, hipStream_t s, const char *what) {
+    if (capturing(s)) return QSV_OK;
+    hipError_t e = hipEventRecord(w.last, s);
+    if (e != hipSuccess) return hip_fail(e, what);
+    w.last_stream = s;
+    w.used = true;
+    return QSV_OK;
+}
+
+void ws_free(Workspace &w) {
+    if (w.ptr) (void)hipFree(w.ptr);
+    if (w.last) (void)hipEventDestroy(w.last);
+    w = Workspace{};
 }
 
 hipEvent_t take_event(Timer &t) {
@@ -212,8 +273,8 @@ qsv_status check_state(qsv_ctx *ctx, const void *state, int n) {
         set_error("n out of range");
         return QSV_E_INVALID;
     }
-    if (((uintptr_t)state) % 16 != 0) {
-        set_error("state must be at least 16-byte aligned");
+    if (((uintptr_t)state) % 256 != 0) {
+        set_error("state must be 256-byte aligned");
         return QSV_E_INVALID;
     }
     return QSV_OK;
@@ -225,19 +286,27 @@ size_t section_lds(const Plan &P, int s) {
     return transpose_lds_bytes(S.c, amp_bytes(P.dtype));
 }
 
-qsv_status ensure_ptab(qsv_ctx *ctx, size_t bytes) {
-    if (ctx->ptab_bytes >= bytes) return QSV_OK;
-    if (ctx->ptab) (void)hipFree(ctx->ptab);
-    ctx->ptab = nullptr;
-    ctx->ptab_bytes = 0;
-    hipError_t e = hipMalloc(&ctx->ptab, bytes);
-    if (e != hipSuccess) {
-        set_error(std::string("parameter table workspace: ") + hipGetErrorString(e));
-        return QSV_E_NOMEM;
-    }
-    ctx->ptab_bytes = bytes;
-    return QSV_OK;
+// per-state parameter tables of `batch` states: 2 values per parameterised op
+size_t ptab_bytes(const Plan &P, int batch, size_t es) {
+    return (size_t)batch * 2 * std::max<int64_t>(1, P.n_param_ops) * es;
 }
+
+// adjoint workspace: per-(state, op, chunk) gradient partials + per-(state, op)
+// sums, and the energy reduction's partials (doubles)
+size_t adjoint_partials_bytes(const Plan &P, int batch) {
+    const uint64_t nchunks = 1ull << (P.n - P.c);
+    const size_t nslots = (size_t)P.n_param_ops;
+    const size_t d = std::max<size_t>((size_t)reduce_blocks(P.n) * batch,
+                                      (size_t)batch * nslots * nchunks + (size_t)batch * nslots);
+    return d * sizeof(double);
+}
+
+// reverse-sweep LDS of section s: transposition area + per-wave partials
+size_t adjoint_section_lds(const Plan &P, int s) {
+    const size_t waves = ((size_t(1) << (P.dsec[s].c - P.r)) + 63) / 64;
+    return section_lds(P, s) + P.dsec[s].n_params_used * waves * sizeof(double);
+}
+
 
 // ptab: per-state parameter tables already filled (or NULL for plans without parameters)
 qsv_status run_sections(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv, void *state, int n,
@@ -286,6 +355,8 @@ qsv_status run_sections(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv, void
 }  // namespace
 
 extern "C" {
+
+static qsv_status check_plan(qsv_ctx *ctx, const qsv_plan *plan, int n);
 
 const char *qsv_last_error(void) { return g_last_error.c_str(); }
 
@@ -343,7 +414,7 @@ qsv_status qsv_plan_get_stats(const qsv_plan *plan, qsv_plan_stats *out) {
     out->chunk_bits = P.c;
     out->register_bits = P.r;
     out->pinned_low_bits = P.opt.pinned_low_bits;
-    out->fusion_max_qubits = P.opt.fusion_max_qubits;
+    out->fusion_max_qubits = P.fusion_eff;
     out->swap_mode = P.opt.swap_mode;
     out->diag_free = P.opt.diag_free;
     out->n_gates = (int64_t)P.gates.size();
@@ -443,9 +514,9 @@ void qsv_destroy(qsv_ctx *ctx) {
         (void)hipDeviceSynchronize();
         for (auto &b : ctx->plans) (void)hipFree(b.block);
         for (auto &b : ctx->batches) batch_release(b.launch);
-        if (ctx->partials) (void)hipFree(ctx->partials);
-        if (ctx->ptab) (void)hipFree(ctx->ptab);
-        if (ctx->terms) (void)hipFree(ctx->terms);
+        ws_free(ctx->partials);
+        ws_free(ctx->ptab);
+        ws_free(ctx->terms);
         for (auto &t : ctx->timers) {
             for (auto &pr : t.pending) {
                 (void)hipEventDestroy(pr.first);
@@ -564,30 +635,41 @@ qsv_status qsv_apply_params(qsv_ctx *ctx, const qsv_plan *plan, void *states, in
     if ((rc = upload_plan(ctx, P, &pv)) != QSV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const size_t es = amp_bytes(ctx->dtype);
-    if ((rc = ensure_ptab(ctx, (size_t)batch * 2 * std::max<int64_t>(1, P.n_param_ops) * es)) != QSV_OK)
+    if ((rc = ws_acquire(ctx->ptab, ptab_bytes(P, batch, es), s, "parameter table workspace")) != QSV_OK)
         return rc;
     hipError_t e = launch_param_table(ctx->dtype, params_dev, (int)P.n_params, pv->pslots,
-                                      (int)P.n_param_ops, batch, ctx->ptab, s);
+                                      (int)P.n_param_ops, batch, ctx->ptab.ptr, s);
     if (e != hipSuccess) return hip_fail(e, "parameter table launch");
-    return run_sections(ctx, P, *pv, states, n, batch, 0, (int64_t)P.sections.size(), ctx->ptab, s);
+    rc = run_sections(ctx, P, *pv, states, n, batch, 0, (int64_t)P.sections.size(), ctx->ptab.ptr, s);
+    qsv_status rr = ws_release(ctx->ptab, s, "parameter table workspace");
+    return rc != QSV_OK ? rc : rr;
 }
 
+// Observable terms to the context's device table.  The terms travel by value
+// in kernel arguments: no host staging, no synchronisation, so the host array
+// may go away as soon as the call returns.  The caller holds the terms
+// workspace (ws_acquire) around the launches that read it.
 static qsv_status upload_terms(qsv_ctx *ctx, const qsv_zterm *terms, size_t nt, hipStream_t s) {
-    if (nt > ctx->terms_cap) {
-        if (ctx->terms) (void)hipFree(ctx->terms);
-        ctx->terms = nullptr;
-        ctx->terms_cap = 0;
-        hipError_t e = hipMalloc((void **)&ctx->terms, nt * sizeof(qsv_zterm));
-        if (e != hipSuccess) {
-            set_error("observable table allocation failed");
-            return QSV_E_NOMEM;
-        }
-        ctx->terms_cap = nt;
+    hipError_t e = launch_store_terms(terms, nt, (qsv_zterm *)ctx->terms.ptr, s);
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "observable upload");
+}
+
+static qsv_status check_terms(const qsv_zterm *terms, size_t nt, int n) {
+    if (nt == 0 || nt > QSV_MAX_TERMS) {
+        set_error("n_terms must be in [1, " + std::to_string(QSV_MAX_TERMS) + "]");
+        return QSV_E_INVALID;
     }
-    hipError_t e = hipMemcpyAsync(ctx->terms, terms, nt * sizeof(qsv_zterm), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "observable upload");
-    e = hipStreamSynchronize(s);  // the host array may go away after return
-    return e == hipSuccess ? QSV_OK : hip_fail(e, "observable upload sync");
+    for (size_t t = 0; t < nt; ++t) {
+        if (n < 64 && (terms[t].zmask >> n) != 0) {
+            set_error("Z-string acts on a qubit >= n");
+            return QSV_E_INVALID;
+        }
+        if (!std::isfinite(terms[t].coeff)) {
+            set_error("Z-string coefficient is not finite");
+            return QSV_E_NUMERIC;
+        }
+    }
+    return QSV_OK;
 }
 
 static qsv_status reduce_common(qsv_ctx *ctx, int kind, const void *a, const void *b, int n,
@@ -595,14 +677,19 @@ static qsv_status reduce_common(qsv_ctx *ctx, int kind, const void *a, const voi
                                 hipStream_t s) {
     const int nblk = reduce_blocks(n);
     const int W = kind == 1 ? 4 : 1;
-    qsv_status rc = ensure_partials(ctx, (size_t)nblk * W * batch * sizeof(double));
+    qsv_status rc = ws_acquire(ctx->partials, (size_t)nblk * W * batch * sizeof(double), s,
+                               "reduction workspace");
     if (rc != QSV_OK) return rc;
     if (kind == 2) {
+        if ((rc = ws_acquire(ctx->terms, QSV_MAX_TERMS * sizeof(qsv_zterm), s, "observable table")) != QSV_OK)
+            return rc;
         if ((rc = upload_terms(ctx, terms, nt, s)) != QSV_OK) return rc;
     }
-    hipError_t e = launch_reduce(ctx->dtype, kind, a, b, n, batch, ctx->terms, (int)nt,
-                                 ctx->partials, nblk, out, s);
-    return e == hipSuccess ? QSV_OK : hip_fail(e, "reduction launch");
+    hipError_t e = launch_reduce(ctx->dtype, kind, a, b, n, batch, (const qsv_zterm *)ctx->terms.ptr,
+                                 (int)nt, (double *)ctx->partials.ptr, nblk, out, s);
+    if (e != hipSuccess) return hip_fail(e, "reduction launch");
+    if (kind == 2 && (rc = ws_release(ctx->terms, s, "observable table")) != QSV_OK) return rc;
+    return ws_release(ctx->partials, s, "reduction workspace");
 }
 
 qsv_status qsv_norm(qsv_ctx *ctx, const void *state, int n, double *out_dev, void *stream) {
@@ -639,15 +726,7 @@ qsv_status qsv_expval(qsv_ctx *ctx, const void *state, int n, const qsv_zterm *t
         set_error("NULL argument");
         return QSV_E_INVALID;
     }
-    if (n_terms == 0 || n_terms > 4096) {
-        set_error("n_terms must be in [1, 4096]");
-        return QSV_E_INVALID;
-    }
-    for (size_t t = 0; t < n_terms; ++t)
-        if (n < 64 && (terms[t].zmask >> n) != 0) {
-            set_error("Z-string acts on a qubit >= n");
-            return QSV_E_INVALID;
-        }
+    if ((rc = check_terms(terms, n_terms, n)) != QSV_OK) return rc;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     return reduce_common(ctx, 2, state, nullptr, n, 1, terms, n_terms, out_dev, (hipStream_t)stream);
@@ -676,6 +755,48 @@ qsv_status qsv_copy(qsv_ctx *ctx, void *dst, const void *src, int n, void *strea
     DeviceGuard g(ctx->device);
     hipError_t e = launch_copy(ctx->dtype, dst, src, n, (hipStream_t)stream);
     return e == hipSuccess ? QSV_OK : hip_fail(e, "copy launch");
+}
+
+qsv_status qsv_reserve(qsv_ctx *ctx, const qsv_plan *plan, int n, int batch, void *stream) {
+    if (!ctx) {
+        set_error("context is NULL");
+        return QSV_E_INVALID;
+    }
+    if (plan) n = plan->p.n;
+    if (n < 1 || n > QSV_MAX_QUBITS) {
+        set_error("n out of range");
+        return QSV_E_INVALID;
+    }
+    if (batch < 1 || batch > 65535) {
+        set_error("batch must be in [1, 65535]");
+        return QSV_E_INVALID;
+    }
+    qsv_status rc;
+    if (plan && (rc = check_plan(ctx, plan, n)) != QSV_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (capturing(s)) {
+        set_error("qsv_reserve must be called before graph capture");
+        return QSV_E_STATE;
+    }
+    size_t part = (size_t)reduce_blocks(n) * 4 * batch * sizeof(double);
+    size_t pt = 0;
+    if (plan) {
+        const Plan &P = plan->p;
+        const DevPlanView *pv = nullptr;
+        if ((rc = upload_plan(ctx, P, &pv)) != QSV_OK) return rc;
+        pt = ptab_bytes(P, batch, amp_bytes(ctx->dtype));
+        if (P.n_param_ops > 0) part = std::max(part, adjoint_partials_bytes(P, batch));
+    }
+    struct { Workspace *w; size_t bytes; } need[3] = {
+        {&ctx->partials, part}, {&ctx->ptab, std::max<size_t>(pt, 1)},
+        {&ctx->terms, QSV_MAX_TERMS * sizeof(qsv_zterm)}};
+    for (auto &x : need) {
+        if ((rc = ws_acquire(*x.w, x.bytes, s, "qsv_reserve")) != QSV_OK) return rc;
+        if ((rc = ws_release(*x.w, s, "qsv_reserve")) != QSV_OK) return rc;
+    }
+    return QSV_OK;
 }
 
 qsv_status qsv_timing_enable(qsv_ctx *ctx, int enable) {
@@ -778,6 +899,58 @@ extern "C" qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *con
     return rc;
 }
 
+// Forward pass, energies, lambda = H psi and the reverse sweep, on workspaces
+// already held by the caller.
+static qsv_status adjoint_body(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv,
+                               const qsv_zterm *terms, size_t n_terms, const double *params_dev,
+                               int batch, void *psi_dev, void *lambda_dev, double *energy_dev,
+                               double *grad_dev, int nslots, int nblk, uint64_t nchunks,
+                               hipStream_t s) {
+    const int n = P.n;
+    hipError_t e = hipSuccess;
+    if (nslots > 0) {
+        e = launch_param_table(ctx->dtype, params_dev, (int)P.n_params, pv.pslots, nslots, batch,
+                               ctx->ptab.ptr, s);
+        if (e != hipSuccess) return hip_fail(e, "parameter table launch");
+    }
+    // forward
+    e = launch_fill_basis(ctx->dtype, psi_dev, n, batch, 0, s);
+    if (e != hipSuccess) return hip_fail(e, "init launch");
+    qsv_status rc = run_sections(ctx, P, pv, psi_dev, n, batch, 0, (int64_t)P.sections.size(),
+                                 ctx->ptab.ptr, s);
+    if (rc != QSV_OK) return rc;
+    // energies and lambda = H psi
+    if ((rc = upload_terms(ctx, terms, n_terms, s)) != QSV_OK) return rc;
+    double *partials = (double *)ctx->partials.ptr;
+    const qsv_zterm *tdev = (const qsv_zterm *)ctx->terms.ptr;
+    e = launch_reduce(ctx->dtype, 2, psi_dev, nullptr, n, batch, tdev, (int)n_terms, partials,
+                      nblk, energy_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "energy launch");
+    e = launch_apply_zsum(ctx->dtype, psi_dev, lambda_dev, n, batch, tdev, (int)n_terms, s);
+    if (e != hipSuccess) return hip_fail(e, "observable launch");
+    if (nslots == 0) return QSV_OK;
+    // reverse sweep over the sections
+    double *part = partials;
+    double *ssum = partials + (size_t)batch * nslots * nchunks;
+    for (int64_t si = (int64_t)P.sections.size() - 1; si >= 0; --si) {
+        // transposition area + per-wave gradient partials of the section's ops
+        const size_t lds = adjoint_section_lds(P, (int)si);
+        if (lds > 159 * 1024) {
+            set_error("adjoint: section " + std::to_string(si) + " has too many parameterised "
+                      "ops for the reverse sweep's LDS (use smaller chunks)");
+            return QSV_E_UNSUPPORTED;
+        }
+        rc = timed(ctx, 0, s, [&] {
+            return launch_adjoint_section(P.dtype, P.r, psi_dev, lambda_dev, n, batch, pv, (int)si,
+                                          P.c, lds, ctx->ptab.ptr, nslots, part, s);
+        }, "adjoint section launch");
+        if (rc != QSV_OK) return rc;
+    }
+    e = launch_grad_reduce(part, nslots, batch, nchunks, ssum, pv.poff, pv.plist,
+                           (int)P.n_params, grad_dev, s);
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "gradient reduction launch");
+}
+
 extern "C" qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const qsv_zterm *terms,
                                        size_t n_terms, const double *params_dev, int batch,
                                        void *psi_dev, void *lambda_dev, double *energy_dev,
@@ -800,15 +973,7 @@ extern "C" qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const
         set_error("params_dev / grad_dev is NULL");
         return QSV_E_INVALID;
     }
-    if (n_terms == 0 || n_terms > 4096) {
-        set_error("n_terms must be in [1, 4096]");
-        return QSV_E_INVALID;
-    }
-    for (size_t t = 0; t < n_terms; ++t)
-        if (n < 64 && (terms[t].zmask >> n) != 0) {
-            set_error("Z-string acts on a qubit >= n");
-            return QSV_E_INVALID;
-        }
+    if ((rc = check_terms(terms, n_terms, n)) != QSV_OK) return rc;
     if (P.opt.swap_mode != QSV_SWAP_REMAP || P.kmax > 2 || P.c - P.r > 8 ||
         (P.dtype == QSV_C128 && P.r > 4)) {
         set_error("adjoint plans need remap mode, fusion of at most 2 qubits, "
@@ -822,50 +987,19 @@ extern "C" qsv_status qsv_adjoint_grad(qsv_ctx *ctx, const qsv_plan *plan, const
     if ((rc = upload_plan(ctx, P, &pv)) != QSV_OK) return rc;
     const size_t es = amp_bytes(ctx->dtype);
     const int nslots = (int)P.n_param_ops;
-    if ((rc = ensure_ptab(ctx, (size_t)batch * 2 * std::max(1, nslots) * es)) != QSV_OK) return rc;
-    hipError_t e = hipSuccess;
-    if (nslots > 0) {
-        e = launch_param_table(ctx->dtype, params_dev, (int)P.n_params, pv->pslots, nslots, batch,
-                               ctx->ptab, s);
-        if (e != hipSuccess) return hip_fail(e, "parameter table launch");
-    }
-    // forward
-    e = launch_fill_basis(ctx->dtype, psi_dev, n, batch, 0, s);
-    if (e != hipSuccess) return hip_fail(e, "init launch");
-    rc = run_sections(ctx, P, *pv, psi_dev, n, batch, 0, (int64_t)P.sections.size(), ctx->ptab, s);
-    if (rc != QSV_OK) return rc;
-    // energies and lambda = H psi
     const int nblk = reduce_blocks(n);
     const uint64_t nchunks = 1ull << (n - P.c);
-    const size_t part_doubles = std::max<size_t>((size_t)nblk * batch,
-                                                 (size_t)batch * nslots * nchunks + (size_t)batch * nslots);
-    if ((rc = ensure_partials(ctx, part_doubles * sizeof(double))) != QSV_OK) return rc;
-    if ((rc = upload_terms(ctx, terms, n_terms, s)) != QSV_OK) return rc;
-    e = launch_reduce(ctx->dtype, 2, psi_dev, nullptr, n, batch, ctx->terms, (int)n_terms,
-                      ctx->partials, nblk, energy_dev, s);
-    if (e != hipSuccess) return hip_fail(e, "energy launch");
-    e = launch_apply_zsum(ctx->dtype, psi_dev, lambda_dev, n, batch, ctx->terms, (int)n_terms, s);
-    if (e != hipSuccess) return hip_fail(e, "observable launch");
-    if (nslots == 0) return QSV_OK;
-    // reverse sweep over the sections
-    double *part = ctx->partials;
-    double *ssum = ctx->partials + (size_t)batch * nslots * nchunks;
-    for (int64_t si = (int64_t)P.sections.size() - 1; si >= 0; --si) {
-        // transposition area + per-wave gradient partials of the section's ops
-        const size_t waves = ((size_t(1) << (P.dsec[si].c - P.r)) + 63) / 64;
-        const size_t lds = section_lds(P, (int)si) + P.dsec[si].n_params_used * waves * sizeof(double);
-        if (lds > 159 * 1024) {
-            set_error("adjoint: section " + std::to_string(si) + " has too many parameterised "
-                      "ops for the reverse sweep's LDS (use smaller chunks)");
-            return QSV_E_UNSUPPORTED;
-        }
-        rc = timed(ctx, 0, s, [&] {
-            return launch_adjoint_section(P.dtype, P.r, psi_dev, lambda_dev, n, batch, *pv, (int)si,
-                                          P.c, lds, ctx->ptab, nslots, part, s);
-        }, "adjoint section launch");
-        if (rc != QSV_OK) return rc;
-    }
-    e = launch_grad_reduce(part, nslots, batch, nchunks, ssum, pv->poff, pv->plist,
-                           (int)P.n_params, grad_dev, s);
-    return e == hipSuccess ? QSV_OK : hip_fail(e, "gradient reduction launch");
+    if ((rc = ws_acquire(ctx->ptab, ptab_bytes(P, batch, es), s, "parameter table workspace")) != QSV_OK)
+        return rc;
+    if ((rc = ws_acquire(ctx->partials, adjoint_partials_bytes(P, batch), s, "gradient workspace")) != QSV_OK)
+        return rc;
+    if ((rc = ws_acquire(ctx->terms, QSV_MAX_TERMS * sizeof(qsv_zterm), s, "observable table")) != QSV_OK)
+        return rc;
+    rc = adjoint_body(ctx, P, *pv, terms, n_terms, params_dev, batch, psi_dev, lambda_dev,
+                      energy_dev, grad_dev, nslots, nblk, nchunks, s);
+    qsv_status r1 = ws_release(ctx->ptab, s, "parameter table workspace");
+    qsv_status r2 = ws_release(ctx->partials, s, "gradient workspace");
+    qsv_status r3 = ws_release(ctx->terms, s, "observable table");
+    if (rc != QSV_OK) return rc;
+    return r1 != QSV_OK ? r1 : r2 != QSV_OK ? r2 : r3;
 }

@@ -1,7 +1,7 @@
 // The section kernel: one blocked section (begin_blocking .. end_blocking,
 // Sec. IV-A / IV-C) applied to every chunk of the state.
 //
-// One workgroup owns one chunk of 2^c amplitudes (Sec. III-B: a chunk is the
+// One workgroup owns one chunk of 2^c amplitudes (Sec. II-B: a chunk is the
 // set of amplitudes sharing the values of the n - c non-local bits; here the
 // non-local bits are arbitrary, so the chunk is gathered from HBM instead of
 // being a contiguous block).  Each of the 2^(c-r) threads holds 2^r amplitudes

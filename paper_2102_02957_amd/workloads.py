@@ -105,6 +105,33 @@ def quantum_volume(n, depth, seed):
     return gates
 
 
+def grouped_quantum_volume(n, sizes, depth, seed):
+    """Quantum-Volume-style layers inside disjoint qubit groups.
+
+    The n qubits are split by rng.permutation(n) into groups of the given sizes
+    (group g = the next sizes[g] entries, so every group is scattered over the
+    whole register).  Per layer, for each group in turn: perm = a permutation of
+    the group's qubits, then a Haar SU(4) on consecutive pairs.  The final state
+    is the tensor product of the groups' states, so any amplitude of a large
+    instance is a product of amplitudes of small ones.
+    Returns (gates, groups) with groups[g] = the group's qubits in order."""
+    assert sum(sizes) == n
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n)
+    groups, o = [], 0
+    for k in sizes:
+        groups.append([int(q) for q in order[o:o + k]])
+        o += k
+    gates = []
+    for _ in range(depth):
+        for grp in groups:
+            perm = rng.permutation(len(grp))
+            for i in range(len(grp) // 2):
+                u = haar_su(rng, 4)
+                gates.append(Gate("unitary", (grp[perm[2 * i]], grp[perm[2 * i + 1]]), (), u))
+    return gates, groups
+
+
 def ghz(n):
     gates = [Gate("h", (0,))]
     for q in range(n - 1):

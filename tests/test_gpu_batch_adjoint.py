@@ -57,6 +57,7 @@ def test_batch_uneven_vs_oracle(torch, ctxs, dt, tol):
         got = host[offs[b]:offs[b] + (1 << n)]
         want = oracle.apply_circuit(n, gates)
         assert 1.0 - oracle.fidelity(got, want) < tol, b
+        assert oracle.max_abs_diff(got, want) <= (1e-11 if dt == B.QSV_C128 else 2e-5) * np.max(np.abs(want)), b
         assert abs(nh[b] - 1.0) < (1e-12 if dt == B.QSV_C128 else 2e-5)
         assert abs(oracle.norm2(got) - 1.0) < (1e-13 if dt == B.QSV_C128 else 2e-6)
 
@@ -105,6 +106,7 @@ def test_batch_noisy_trajectories_config(torch, ctxs):
         got = states[offs[b]:offs[b] + (1 << n)].cpu().numpy().astype(np.complex128)
         want = oracle.apply_circuit(n, gates)
         assert 1.0 - oracle.fidelity(got, want) < 1e-5, (b, n)
+        assert oracle.max_abs_diff(got, want) <= 2e-5 * np.max(np.abs(want)), (b, n)
 
 
 def test_batch_rejects_bad_input(torch, ctxs):
@@ -124,11 +126,16 @@ def hea_case(n, layers, batch, seed):
 
 
 @pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
-@pytest.mark.parametrize("n,layers,c", [(6, 3, 4), (9, 2, 6), (12, 3, 9)])
-def test_adjoint_vs_oracle(torch, ctxs, dt, n, layers, c):
+@pytest.mark.parametrize("n,layers,c,r", [
+    (6, 3, 4, 4), (9, 2, 6, 4), (12, 3, 9, 4),
+    # 64 and 256 threads per workgroup: whole-wave partial sums and the sum
+    # across waves; (14, 11, 3) is the benchmark's plan shape
+    (13, 3, 10, 4), (14, 3, 11, 3), (15, 2, 11, 4)])
+def test_adjoint_vs_oracle(torch, ctxs, dt, n, layers, c, r):
     batch = 3
     tmpl, theta, terms = hea_case(n, layers, batch, n)
-    plan = B.Plan(n, tmpl, dt, chunk_bits=c, register_bits=min(4, c), fusion_max_qubits=2)
+    plan = B.Plan(n, tmpl, dt, chunk_bits=c, register_bits=r, fusion_max_qubits=2)
+    assert plan.stats()["n_sections"] >= 1
     tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
     psi = torch.empty(batch << n, dtype=tdt, device="cuda")
     lam = torch.empty_like(psi)
@@ -189,3 +196,27 @@ def test_adjoint_hea20_properties(torch, ctxs):
     for k, (b, p) in enumerate(picks):
         shift = 0.5 * (es[2 * k] - es[2 * k + 1])
         assert abs(g[b, p] - shift) < 1e-10, (b, p, g[b, p], shift)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_adjoint_hea20_vs_oracle_shift(torch, ctxs, dt):
+    """The 20-qubit 40-layer ansatz (1600 parameters) in the benchmark's plan
+    shape, both dtypes: the energy of one member and gradient entries of the last
+    layer against the oracle's parameter-shift rule on the host."""
+    n, layers, batch = 20, 40, 4
+    tmpl, theta, terms = hea_case(n, layers, batch, 5)
+    ctx = ctxs[dt]
+    plan = B.Plan(n, tmpl, dt, chunk_bits=11, register_bits=3, fusion_max_qubits=2)
+    tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
+    psi = torch.empty(batch << n, dtype=tdt, device="cuda")
+    lam = torch.empty_like(psi)
+    e, g = ctx.adjoint_grad(plan, terms, torch.from_numpy(theta).cuda(), psi, lam)
+    e, g = e.cpu().numpy(), g.cpu().numpy()
+    b = 2
+    picks = [2 * n * (layers - 1) + k for k in (0, 13, 2 * n - 1)]
+    want = oracle.parameter_shift_tail(n, tmpl, theta[b], terms, picks)
+    for p in picks:
+        if dt == B.QSV_C128:
+            assert abs(g[b, p] - want[p]) < 1e-9, (p, g[b, p], want[p])
+        else:
+            assert abs(g[b, p] - want[p]) < 1e-3 * max(1.0, abs(want[p])), (p, g[b, p], want[p])

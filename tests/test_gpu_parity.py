@@ -59,10 +59,19 @@ def run_gpu(torch, ctxs, n, gates, dt, psi0=None, mode=B.QSV_MODE_BLOCKED, **opt
     return st.cpu().numpy().astype(np.complex128), plan
 
 
+# element-wise bound on max|got - want|, relative to the largest expected
+# amplitude: far above the rounding of the dtype over a few hundred gates, far
+# below what a wrong phase or a wrong matrix entry in any one gate produces
+MAXD = {B.QSV_C128: 1e-11, B.QSV_C64: 2e-5}
+
+
 def assert_close(got, want, dt, what=""):
     f = oracle.fidelity(got, want)
     err = 1.0 - f
-    assert err < TOL[dt], "%s: 1-F = %.3e, max|d| = %.3e" % (what, err, oracle.max_abs_diff(got, want))
+    d = oracle.max_abs_diff(got, want)
+    scale = float(np.max(np.abs(want))) if len(want) else 1.0
+    assert err < TOL[dt], "%s: 1-F = %.3e, max|d| = %.3e" % (what, err, d)
+    assert d <= MAXD[dt] * scale, "%s: max|d| = %.3e (scale %.3e), 1-F = %.3e" % (what, d, scale, err)
     assert abs(oracle.norm2(got) - 1.0) < (1e-12 if dt == B.QSV_C128 else 1e-5)
 
 

@@ -53,3 +53,19 @@ def test_shared_parameter_adds():
     _, g = oracle.adjoint_gradient(n, gates, theta, terms)
     fd = oracle.finite_difference_gradient(n, gates, theta, terms)
     assert abs(g[0] - fd[0]) < 1e-8 and abs(g[1] - fd[1]) < 1e-8
+
+
+def test_parameter_shift_tail_equals_full_shift():
+    """The prefix-sharing shift rule gives the plain shift rule's entries, for
+    parameters anywhere in the circuit (first, middle, last layer)."""
+    n, layers = 5, 4
+    gates = workloads.hardware_efficient_ansatz(n, layers)
+    theta = workloads.ansatz_parameters(n, layers, 1, 9)[0]
+    terms = oracle.ring_zz_terms(n)
+    picks = [0, 7, 2 * n * (layers - 1) + 3, 2 * n * layers - 1]
+    full = oracle.parameter_shift_gradient(n, gates, theta, terms, indices=picks)
+    tail = oracle.parameter_shift_tail(n, gates, theta, terms, picks)
+    _, g = oracle.adjoint_gradient(n, gates, theta, terms)
+    for p in picks:
+        assert abs(tail[p] - full[p]) < 1e-13
+        assert abs(tail[p] - g[p]) < 1e-12

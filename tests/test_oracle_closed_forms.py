@@ -85,3 +85,18 @@ def test_overlap_and_fidelity():
     assert abs(oracle.fidelity(a, 2.5j * a) - 1.0) < 1e-14
     b = oracle.basis_state(n, 3)
     assert abs(oracle.overlap(b, a) - a[3]) < 1e-15
+
+
+def test_grouped_circuit_is_a_product_state():
+    """The product assembly used at full size (tests/grouped.py) against the
+    oracle's plain run of the whole circuit, every amplitude."""
+    from paper_2102_02957_amd import workloads as W
+    import grouped
+    n = 9
+    gates, groups = W.grouped_quantum_volume(n, [4, 3, 2], 5, 7)
+    want = oracle.apply_circuit(n, gates)
+    st = grouped.group_states(gates, groups)
+    got = grouped.product_amplitudes(st, groups, np.arange(1 << n, dtype=np.uint64))
+    assert np.max(np.abs(got - want)) < 1e-14
+    # every qubit is used and every group is scattered
+    assert sorted(q for g in groups for q in g) == list(range(n))

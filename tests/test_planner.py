@@ -194,3 +194,56 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(B.QsvError) as e:
         B.Context(B.QSV_C128)
     assert e.value.status in (-3, -1)
+
+
+def test_launch_grid_limits_rejected():
+    """A section launch has 2^(n-c) workgroups of 2^(c-r) work-items; shapes past
+    the grid limits are refused at plan time instead of truncating the grid."""
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(34, W.ghz(34), B.QSV_C64, chunk_bits=3, register_bits=2)
+    assert e.value.status == -4 and "grid" in str(e.value)
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(34, W.ghz(34), B.QSV_C128, chunk_bits=3, register_bits=3)
+    assert e.value.status == -4
+    # the largest shapes used elsewhere stay accepted
+    B.Plan(34, W.ghz(34), B.QSV_C64, chunk_bits=13, register_bits=5)
+    B.Plan(34, W.ghz(34), B.QSV_C64, chunk_bits=4, register_bits=3)
+
+
+@pytest.mark.parametrize("bad", [
+    [("ry", (0,), (float("nan"),), None, -1)],
+    [("u3", (1,), (0.1, float("inf"), 0.0), None, -1)],
+    [("unitary", (0,), (), np.array([[1, 0], [0, np.nan]], dtype=complex), -1)],
+])
+def test_non_finite_gates_numeric_error(bad):
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(4, bad, B.QSV_C128)
+    assert e.value.status == -5
+
+
+@pytest.mark.parametrize("req,r,want", [(5, 4, 4), (5, 5, 4), (3, 2, 2), (3, 4, 3), (0, 4, 0), (1, 4, 1)])
+def test_stats_report_applied_fusion_width(req, r, want):
+    n = 10
+    p = B.Plan(n, W.u3_cx_layers(n, 4, 2), B.QSV_C64, chunk_bits=8, register_bits=r,
+               fusion_max_qubits=req)
+    assert p.stats()["fusion_max_qubits"] == want
+
+
+def test_incremental_build_tracks_headers(tmp_path, monkeypatch):
+    """The developer's incremental build recompiles a source when a header is newer."""
+    from paper_2102_02957_amd import build as bld
+    src = tmp_path / "a.hip"
+    src.write_text("// x\n")
+    obj = tmp_path / "a.hip.o"
+    assert bld._stale(str(obj), str(src))
+    obj.write_text("")
+    import os, time
+    old = time.time() - 100
+    os.utime(str(src), (old, old))
+    monkeypatch.setattr(bld, "CSRC", str(tmp_path))
+    monkeypatch.setattr(bld, "INCLUDE", str(tmp_path))
+    assert not bld._stale(str(obj), str(src))
+    h = tmp_path / "b.hpp"
+    h.write_text("")
+    os.utime(str(obj), (old + 10, old + 10))
+    assert bld._stale(str(obj), str(src))
