@@ -224,6 +224,18 @@ qsv_status qsv_norm(qsv_ctx *ctx, const void *state, int n, double *out_dev, voi
 /* out_dev[0..3] = Re<a|b>, Im<a|b>, <a|a>, <b|b> */
 qsv_status qsv_overlap(qsv_ctx *ctx, const void *a, const void *b, int n, double *out_dev,
                        void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): qsv_overlap with its reduction
+ * partials in a fixed library array of QSV_NOALLOC_PARTIALS doubles per GPU (64 KiB,
+ * enough for any n <= QSV_MAX_QUBITS; larger requests are refused with QSV_E_INVALID),
+ * instead of a context workspace.  The call allocates nothing and only enqueues two
+ * kernels; the array's address is looked up once per device in qsv_create.  All calls
+ * on one GPU share that array and it keeps the last call's contents (every entry is
+ * written before it is read): calls that overlap in time on one GPU, from any context or
+ * stream, race, and the caller must order them. */
+#define QSV_NOALLOC_PARTIALS 8192
+qsv_status qsv_overlap_noalloc(qsv_ctx *ctx, const void *a, const void *b, int n,
+                               double *out_dev, void *stream);
 /* out_dev[0] = sum_x |a_x|^2 sum_t coeff_t (-1)^popcount(x & zmask_t).  terms: host
  * array of 1..QSV_MAX_TERMS entries, read during the call (it travels to the device in
  * kernel arguments; the call does not synchronise).  QSV_E_NUMERIC for a non-finite

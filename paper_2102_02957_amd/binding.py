@@ -72,7 +72,7 @@ EXPORTED = [
     "qsv_apply_circuit", "qsv_apply_sections", "qsv_apply_params", "qsv_norm", "qsv_overlap",
     "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
     "qsv_timing_enable", "qsv_timing_read", "qsv_autotune", "qsv_autotune_batch",
-    "qsv_reserve",
+    "qsv_reserve", "qsv_overlap_noalloc",
 ]
 
 _lib = None
@@ -110,6 +110,7 @@ def lib():
         "qsv_adjoint_grad": (I, [P, P, ctypes.POINTER(ZTerm), SZ, P, I, P, P, P, P, P]),
         "qsv_batch_run": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(U64), P, P, P]),
         "qsv_reserve": (I, [P, P, I, I, P]),
+        "qsv_overlap_noalloc": (I, [P, P, P, I, P, P]),
         "qsv_timing_enable": (I, [P, I]),
         "qsv_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), I]),
         "qsv_autotune": (I, [P, I, I, ctypes.POINTER(Gate), SZ, ctypes.POINTER(Options), I, P, I, P,
@@ -328,6 +329,14 @@ class Context:
         out = torch.empty(4, dtype=torch.float64, device=a.device) if out is None else out
         _check_f64(out, (4,), "out")
         _check(lib().qsv_overlap(self._h, _ptr(a), _ptr(b), n, _ptr(out), _stream(stream)))
+        return out
+
+    def overlap_noalloc(self, a, b, n, out, stream=None):
+        """qsv_overlap_noalloc: the caller supplies `out` (float64[4] on the device)."""
+        _check_state(a, n, dtype=self.dtype)
+        _check_state(b, n, dtype=self.dtype)
+        _check_f64(out, (4,), "out")
+        _check(lib().qsv_overlap_noalloc(self._h, _ptr(a), _ptr(b), n, _ptr(out), _stream(stream)))
         return out
 
     def expval(self, state, n, terms, out=None, stream=None):

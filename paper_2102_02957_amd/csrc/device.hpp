@@ -58,6 +58,9 @@ hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, i
 hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,
                                 hipStream_t s);
 int reduce_blocks(int n);
+// device address (for the current device, which must be `device`) and size in
+// doubles of the library's fixed reduction-partials array (qsv_overlap_noalloc)
+hipError_t noalloc_scratch(int device, double **ptr, size_t *cap);
 // copy host Z-string terms to a device table (by value through kernel arguments)
 hipError_t launch_store_terms(const qsv_zterm *host, size_t nt, qsv_zterm *dev, hipStream_t s);
 

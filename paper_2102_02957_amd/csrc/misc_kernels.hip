@@ -1,6 +1,7 @@
 // State initialisation, copies, bit-swap permutation passes and the FP64
 // reductions (norm, overlap, diagonal Z-string expectation, renormalisation).
 #include <algorithm>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -272,6 +273,38 @@ hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, i
     if (dt == QSV_C128)
         return reduce_t<Cplx<double>>(kind, a, b, n, batch, terms_dev, n_terms, partials, nblk, out, s);
     return reduce_t<Cplx<float>>(kind, a, b, n, batch, terms_dev, n_terms, partials, nblk, out, s);
+}
+
+// Reduction partials for callers that cannot allocate (qsv_overlap_noalloc):
+// one fixed array per GPU, held by the library until the process ends.  Every
+// partial is written before it is read, so nothing has to be cleared between
+// calls.  On the host, `scratch` names a host-side stand-in, not device memory:
+// kernels get the address that hipGetSymbolAddress returns for the current
+// device.
+constexpr size_t NOALLOC_PARTIALS = QSV_NOALLOC_PARTIALS;
+static_assert(NOALLOC_PARTIALS >= 2048 * 4, "reduce_blocks() <= 2048 blocks, 4 sums each");
+static __device__ __align__(256) double scratch[NOALLOC_PARTIALS];
+
+hipError_t noalloc_scratch(int device, double **ptr, size_t *cap) {
+    static std::mutex mu;
+    static double *addr[64];
+    static bool known[64];
+    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!known[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+        known[device] = true;
+    }
+    *ptr = addr[device];
+    *cap = NOALLOC_PARTIALS;
+    return hipSuccess;
 }
 
 // Observable upload without a host staging buffer: up to TERMS_PER_LAUNCH

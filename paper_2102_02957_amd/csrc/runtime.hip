@@ -78,6 +78,8 @@ struct qsv_ctx {
     qsv::Workspace partials;               // reduction / gradient partials (double)
     qsv::Workspace ptab;                   // per-state parameter tables
     qsv::Workspace terms;                  // observable Z-strings (qsv_zterm)
+    double *noalloc_partials = nullptr;    // this device's fixed array (qsv_overlap_noalloc)
+    size_t noalloc_cap = 0;                // its size in doubles
     bool timing = false;
     qsv::Timer timers[2];
     std::list<qsv::BatchEntry> batches;    // prepared batch launches, most recent first
@@ -496,11 +498,20 @@ qsv_status qsv_create(qsv_ctx **ctx, int hip_device, qsv_dtype dt) {
         set_error("hip_device out of range");
         return QSV_E_INVALID;
     }
+    double *scr = nullptr;
+    size_t scr_cap = 0;
+    {
+        DeviceGuard g(hip_device);
+        e = noalloc_scratch(hip_device, &scr, &scr_cap);
+        if (e != hipSuccess) return hip_fail(e, "fixed reduction array lookup");
+    }
     qsv_ctx *c = new (std::nothrow) qsv_ctx;
     if (!c) {
         set_error("out of host memory");
         return QSV_E_NOMEM;
     }
+    c->noalloc_partials = scr;
+    c->noalloc_cap = scr_cap;
     c->device = hip_device;
     c->dtype = dt;
     *ctx = c;
@@ -716,6 +727,28 @@ qsv_status qsv_overlap(qsv_ctx *ctx, const void *a, const void *b, int n, double
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     return reduce_common(ctx, 1, a, b, n, 1, nullptr, 0, out_dev, (hipStream_t)stream);
+}
+
+qsv_status qsv_overlap_noalloc(qsv_ctx *ctx, const void *a, const void *b, int n,
+                               double *out_dev, void *stream) {
+    qsv_status rc = check_state(ctx, a, n);
+    if (rc != QSV_OK) return rc;
+    if ((rc = check_state(ctx, b, n)) != QSV_OK) return rc;
+    if (!out_dev) {
+        set_error("out_dev is NULL");
+        return QSV_E_INVALID;
+    }
+    const int nblk = reduce_blocks(n);
+    if ((size_t)nblk * 4 > ctx->noalloc_cap || !ctx->noalloc_partials) {
+        set_error("qsv_overlap_noalloc: " + std::to_string(nblk) + " reduction blocks exceed the "
+                  "fixed array of " + std::to_string(ctx->noalloc_cap / 4));
+        return QSV_E_INVALID;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipError_t e = launch_reduce(ctx->dtype, 1, a, b, n, 1, nullptr, 0, ctx->noalloc_partials,
+                                 nblk, out_dev, (hipStream_t)stream);
+    return e == hipSuccess ? QSV_OK : hip_fail(e, "reduction launch");
 }
 
 qsv_status qsv_expval(qsv_ctx *ctx, const void *state, int n, const qsv_zterm *terms,
