@@ -75,7 +75,19 @@ enum {
     QSV_H = 1, QSV_X, QSV_Y, QSV_Z, QSV_S, QSV_SDG, QSV_T, QSV_TDG,
     QSV_RX, QSV_RY, QSV_RZ, QSV_P, QSV_U3,
     QSV_CX, QSV_CZ, QSV_CP, QSV_SWAP,
-    QSV_UNITARY
+    QSV_UNITARY,
+    /* Noise channels rho <- sum_m K_m rho K_m^dagger, accepted by qsv_plan_density only
+     * (Sec. III-A: the simulator's noise model for noisy simulation and its density-matrix
+     * and super-operator methods):
+     *   QSV_AMP_DAMP   1 qubit, p[0] = gamma:  K0 = [[1, 0], [0, sqrt(1-gamma)]],
+     *                                          K1 = [[0, sqrt(gamma)], [0, 0]]
+     *   QSV_PHASE_DAMP 1 qubit, p[0] = lambda: K0 = [[1, 0], [0, sqrt(1-lambda)]],
+     *                                          K1 = [[0, 0], [0, sqrt(lambda)]]
+     *   QSV_DEPOLARIZE 1 qubit, p[0] = p:      sqrt(1-p) I, sqrt(p/3) X, sqrt(p/3) Y, sqrt(p/3) Z
+     *   QSV_KRAUS      nq = 1 or 2, param = number of operators M in [1, 16]; m = M matrices
+     *                  of 2^nq x 2^nq complex, row-major, back to back (local index as for
+     *                  QSV_UNITARY).  Completeness sum K^dagger K = I is not required. */
+    QSV_AMP_DAMP, QSV_PHASE_DAMP, QSV_DEPOLARIZE, QSV_KRAUS
 };
 
 #define QSV_MAX_QUBITS 34       /* 2^34 amplitudes: 128 GiB complex64, 256 GiB complex128 */
@@ -134,6 +146,20 @@ typedef struct qsv_plan qsv_plan;
 qsv_status qsv_plan_blocks(const qsv_options *opt, qsv_dtype dt, int n,
                            const qsv_gate *g, size_t ng, qsv_plan **plan);
 void qsv_plan_destroy(qsv_plan *plan);
+
+/* Density-matrix plan (Sec. III-A: the density-matrix method of the simulator; the
+ * cache blocking applies unchanged).  The n-qubit density matrix rho is held as a
+ * state of 2n qubits: amplitude index i | (j << n) holds rho[i][j] (row i = qubits
+ * 0..n-1, column j = qubits n..2n-1).  A gate U on qubits Q becomes U on Q and conj(U)
+ * on Q + n, since (U rho U^dagger)[i][j] = sum U[i][i'] conj(U[j][j']) rho[i'][j']; a
+ * channel with k-qubit Kraus operators K_m on Q becomes one dense 2k-qubit gate on
+ * (Q, Q + n) with S[a | b << k][c | e << k] = sum_m K_m[a][c] conj(K_m[b][e]).  The
+ * result is an ordinary plan of 2n qubits for qsv_apply_circuit / qsv_apply_sections;
+ * qsv_init_basis with basis b | (b << n) prepares |b><b|, qsv_norm gives the purity
+ * Tr(rho^2), qsv_dm_trace and qsv_dm_expval read the diagonal.  n in [1, 17]; gates
+ * with bound parameters are refused (QSV_E_UNSUPPORTED). */
+qsv_status qsv_plan_density(const qsv_options *opt, qsv_dtype dt, int n, const qsv_gate *g,
+                            size_t ng, qsv_plan **plan);
 
 typedef struct {
     int32_t n, dtype, chunk_bits, register_bits, pinned_low_bits;
@@ -242,6 +268,13 @@ qsv_status qsv_overlap_noalloc(qsv_ctx *ctx, const void *a, const void *b, int n
  * coefficient. */
 qsv_status qsv_expval(qsv_ctx *ctx, const void *state, int n, const qsv_zterm *terms,
                       size_t n_terms, double *out_dev, void *stream);
+/* Density matrices of n qubits (2^(2n) amplitudes, see qsv_plan_density), FP64 sums of the
+ * diagonal in a fixed order: out_dev[0] = Tr(rho) = sum_i Re rho[i][i];
+ * qsv_dm_expval: out_dev[0] = Tr(rho H) = sum_i Re rho[i][i] sum_t coeff_t (-1)^popcount(i & zmask_t). */
+qsv_status qsv_dm_trace(qsv_ctx *ctx, const void *rho, int n, double *out_dev, void *stream);
+qsv_status qsv_dm_expval(qsv_ctx *ctx, const void *rho, int n, const qsv_zterm *terms,
+                         size_t n_terms, double *out_dev, void *stream);
+
 /* Divide the state by sqrt(<psi|psi>) (computed in FP64); norm_out_dev[0] = <psi|psi>
  * before scaling.  A zero or non-finite norm leaves the state unscaled and sets
  * norm_out_dev[0] to it; the caller checks it. */

@@ -21,7 +21,10 @@ Computing Simulation on Supercomputers", arXiv:2102.02957):
 * FP64 reductions (norm, overlap, fidelity, diagonal Z-string expectation);
 * a plain adjoint gradient plus parameter-shift and finite differences;
 * an executor for an exported blocked plan (Sec. IV-A, the transpiler's
-  output: chunk swaps, begin/end of blocking sections).
+  output: chunk swaps, begin/end of blocking sections);
+* density-matrix evolution with noise channels, rho -> sum K rho K^dagger on
+  the full 2^n x 2^n matrix (Sec. III-A: noisy simulation, density-matrix
+  method), in ``oracle.density``.
 
 Gates are plain tuples ``(kind, qubits, params, matrix, pidx)``; see
 ``oracle.gates`` for the kinds.
@@ -36,6 +39,7 @@ from .adjoint import (adjoint_gradient, parameter_shift_gradient, parameter_shif
                       finite_difference_gradient, energy)
 from .plan_exec import run_plan
 from .closed_forms import qft_basis_amplitude, ghz_state
+from . import density
 
 __all__ = [
     "gate_matrix", "u3_matrix", "is_diagonal_kind", "GATE_ARITY",
@@ -44,5 +48,5 @@ __all__ = [
     "norm2", "overlap", "fidelity", "max_abs_diff", "zstring_expval",
     "ring_zz_terms", "zz_diag_values",
     "adjoint_gradient", "parameter_shift_gradient", "parameter_shift_tail", "finite_difference_gradient",
-    "energy", "run_plan", "qft_basis_amplitude", "ghz_state",
+    "energy", "run_plan", "qft_basis_amplitude", "ghz_state", "density",
 ]

@@ -21,7 +21,8 @@ QSV_OP_BEGIN, QSV_OP_END, QSV_OP_CHUNK_SWAP, QSV_OP_GATE = 1, 2, 3, 4
 
 KINDS = {k: i + 1 for i, k in enumerate(
     ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "rx", "ry", "rz", "p", "u3",
-     "cx", "cz", "cp", "swap", "unitary"])}
+     "cx", "cz", "cp", "swap", "unitary",
+     "amp_damp", "phase_damp", "depolarize", "kraus"])}
 
 STATUS = {0: "QSV_OK", -1: "QSV_E_INVALID", -2: "QSV_E_NOMEM", -3: "QSV_E_HIP",
           -4: "QSV_E_UNSUPPORTED", -5: "QSV_E_NUMERIC", -6: "QSV_E_STATE"}
@@ -72,7 +73,7 @@ EXPORTED = [
     "qsv_apply_circuit", "qsv_apply_sections", "qsv_apply_params", "qsv_norm", "qsv_overlap",
     "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
     "qsv_timing_enable", "qsv_timing_read", "qsv_autotune", "qsv_autotune_batch",
-    "qsv_reserve", "qsv_overlap_noalloc",
+    "qsv_reserve", "qsv_overlap_noalloc", "qsv_plan_density", "qsv_dm_trace", "qsv_dm_expval",
 ]
 
 _lib = None
@@ -110,6 +111,10 @@ def lib():
         "qsv_adjoint_grad": (I, [P, P, ctypes.POINTER(ZTerm), SZ, P, I, P, P, P, P, P]),
         "qsv_batch_run": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(U64), P, P, P]),
         "qsv_reserve": (I, [P, P, I, I, P]),
+        "qsv_plan_density": (I, [ctypes.POINTER(Options), I, I, ctypes.POINTER(Gate), SZ,
+                                 ctypes.POINTER(P)]),
+        "qsv_dm_trace": (I, [P, P, I, P, P]),
+        "qsv_dm_expval": (I, [P, P, I, ctypes.POINTER(ZTerm), SZ, P, P]),
         "qsv_overlap_noalloc": (I, [P, P, P, I, P, P]),
         "qsv_timing_enable": (I, [P, I]),
         "qsv_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), I]),
@@ -166,8 +171,10 @@ def gates_to_c(gates):
         c.param = -1 if pidx is None else int(pidx)
         for j, v in enumerate(params):
             c.p[j] = float(v)
-        if kind == "unitary" and matrix is not None:
+        if kind in ("unitary", "kraus") and matrix is not None:
             m = np.ascontiguousarray(np.asarray(matrix, dtype=np.complex128))
+            if kind == "kraus":
+                c.param = int(m.shape[0])      # number of Kraus operators
             buf = m.view(np.float64)
             keep.append(buf)
             c.m = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -190,6 +197,24 @@ class Plan:
                                      ctypes.byref(h)))
         self._h = h
         del keep
+
+    @classmethod
+    def density(cls, n, gates, dtype=QSV_C128, **options):
+        """qsv_plan_density: the 2n-qubit plan of an n-qubit circuit with channels
+        acting on its density matrix (rho[i][j] at index i | j << n)."""
+        self = cls.__new__(cls)
+        self.n = 2 * int(n)
+        self.n_density = int(n)
+        self.dtype = dtype
+        self.gates = list(gates)
+        opt = make_options(dtype, **options)
+        arr, keep = gates_to_c(self.gates)
+        h = ctypes.c_void_p()
+        _check(lib().qsv_plan_density(ctypes.byref(opt), dtype, int(n), arr, len(self.gates),
+                                      ctypes.byref(h)))
+        self._h = h
+        del keep
+        return self
 
     @property
     def handle(self):
@@ -350,6 +375,31 @@ class Context:
         _check_f64(out, (1,), "out")
         _check(lib().qsv_expval(self._h, _ptr(state), n, arr, len(terms), _ptr(out),
                                 _stream(stream)))
+        return out
+
+    def dm_init_basis(self, rho, n, basis=0, stream=None):
+        """rho <- |basis><basis| for an n-qubit density matrix (2^(2n) amplitudes)."""
+        self.init_basis(rho, 2 * n, int(basis) | (int(basis) << n), stream)
+
+    def dm_trace(self, rho, n, out=None, stream=None):
+        torch = _torch()
+        _check_state(rho, 2 * n, dtype=self.dtype)
+        out = torch.empty(1, dtype=torch.float64, device=rho.device) if out is None else out
+        _check_f64(out, (1,), "out")
+        _check(lib().qsv_dm_trace(self._h, _ptr(rho), n, _ptr(out), _stream(stream)))
+        return out
+
+    def dm_expval(self, rho, n, terms, out=None, stream=None):
+        torch = _torch()
+        _check_state(rho, 2 * n, dtype=self.dtype)
+        arr = (ZTerm * len(terms))()
+        for i, (c, m) in enumerate(terms):
+            arr[i].coeff = float(c)
+            arr[i].zmask = int(m)
+        out = torch.empty(1, dtype=torch.float64, device=rho.device) if out is None else out
+        _check_f64(out, (1,), "out")
+        _check(lib().qsv_dm_expval(self._h, _ptr(rho), n, arr, len(terms), _ptr(out),
+                                   _stream(stream)))
         return out
 
     def normalize(self, state, n, out=None, stream=None):

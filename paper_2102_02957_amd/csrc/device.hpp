@@ -58,6 +58,10 @@ hipError_t launch_reduce(qsv_dtype dt, int kind, const void *a, const void *b, i
 hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,
                                 hipStream_t s);
 int reduce_blocks(int n);
+// density matrix of n qubits (2n-qubit state): kind 0 trace, 1 Z-string expectation
+hipError_t launch_dm_reduce(qsv_dtype dt, int kind, const void *rho, int n,
+                            const qsv_zterm *terms_dev, int n_terms, double *partials, int nblk,
+                            double *out, hipStream_t s);
 // device address (for the current device, which must be `device`) and size in
 // doubles of the library's fixed reduction-partials array (qsv_overlap_noalloc)
 hipError_t noalloc_scratch(int device, double **ptr, size_t *cap);

@@ -131,6 +131,24 @@ k_reduce_final(const double *__restrict__ partials, int nblk, double *__restrict
     block_sum<W>(acc, out + (size_t)blockIdx.x * W);
 }
 
+// Diagonal of a density matrix held as a 2n-qubit state (rho[i][i] at index
+// i | (i << n)): per-block FP64 sums of Re rho[i][i] (KIND 0, the trace) or of
+// Re rho[i][i] h(i) for Z-strings h (KIND 1), in a fixed order.
+template <typename V, int KIND>
+__global__ void __launch_bounds__(RED_THREADS)
+k_dm_diag_partial(const V *__restrict__ rho, int n, const qsv_zterm *__restrict__ terms, int nt,
+                  double *__restrict__ partials) {
+    const uint64_t N = 1ull << n;
+    double acc[1] = {0.0};
+    const uint64_t stride = (uint64_t)gridDim.x * RED_THREADS;
+    for (uint64_t i = (uint64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < N; i += stride) {
+        const double d = (double)rho[i | (i << n)].x;
+        if constexpr (KIND == 0) acc[0] += d;
+        else acc[0] += d * zsum(i, terms, nt);
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
 template <typename V>
 __global__ void __launch_bounds__(256)
 k_scale(V *__restrict__ st, int n, const double *__restrict__ norm2) {
@@ -334,6 +352,26 @@ hipError_t launch_store_terms(const qsv_zterm *host, size_t nt, qsv_zterm *dev, 
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_dm_reduce(qsv_dtype dt, int kind, const void *rho, int n,
+                            const qsv_zterm *terms_dev, int n_terms, double *partials, int nblk,
+                            double *out, hipStream_t s) {
+#define QSV_DM(V)                                                                              \
+    if (kind == 0)                                                                             \
+        hipLaunchKernelGGL((k_dm_diag_partial<V, 0>), dim3(nblk), dim3(RED_THREADS), 0, s,      \
+                           (const V *)rho, n, nullptr, 0, partials);                           \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_dm_diag_partial<V, 1>), dim3(nblk), dim3(RED_THREADS), 0, s,      \
+                           (const V *)rho, n, terms_dev, n_terms, partials);
+    if (dt == QSV_C128) {
+        QSV_DM(Cplx<double>)
+    } else {
+        QSV_DM(Cplx<float>)
+    }
+#undef QSV_DM
+    hipLaunchKernelGGL((k_reduce_final<1>), dim3(1), dim3(RED_THREADS), 0, s, partials, nblk, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_scale_by_norm(qsv_dtype dt, void *state, int n, int batch, const double *norm2,

@@ -214,6 +214,12 @@ static qsv_status validate_and_build(int n, const qsv_gate *g, size_t ng, std::v
         GateRec r;
         r.kind = s.kind;
         int nq = 0;
+        if (s.kind == QSV_AMP_DAMP || s.kind == QSV_PHASE_DAMP || s.kind == QSV_DEPOLARIZE ||
+            s.kind == QSV_KRAUS) {
+            err = "gate " + std::to_string(i) + ": noise channels need a density-matrix plan "
+                  "(qsv_plan_density)";
+            return QSV_E_UNSUPPORTED;
+        }
         if (!gate_arity(s.kind, nq)) {
             err = "gate " + std::to_string(i) + ": unknown kind " + std::to_string(s.kind);
             return QSV_E_INVALID;

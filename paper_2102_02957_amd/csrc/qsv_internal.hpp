@@ -163,6 +163,10 @@ struct Plan {
 qsv_status build_plan(const qsv_options &opt, qsv_dtype dt, int n, const qsv_gate *g, size_t ng,
                       Plan &out, std::string &err);
 void default_options(qsv_dtype dt, qsv_options &opt);
+// density.cpp: the 2n-qubit gate list of an n-qubit circuit's density-matrix
+// evolution (channels become dense gates on (Q, Q + n)); `store` owns matrices
+qsv_status density_gates(int n, const qsv_gate *g, size_t ng, std::vector<qsv_gate> &out,
+                         std::vector<std::vector<double>> &store, std::string &err);
 // gates.cpp
 bool gate_arity(int kind, int &nq);
 bool named_matrix(int kind, const double *p, std::vector<cd> &m);

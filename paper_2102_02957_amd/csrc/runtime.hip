@@ -402,6 +402,30 @@ qsv_status qsv_plan_blocks(const qsv_options *opt, qsv_dtype dt, int n, const qs
     return QSV_OK;
 }
 
+qsv_status qsv_plan_density(const qsv_options *opt, qsv_dtype dt, int n, const qsv_gate *g,
+                            size_t ng, qsv_plan **plan) {
+    if (!plan) {
+        set_error("plan out-pointer is NULL");
+        return QSV_E_INVALID;
+    }
+    *plan = nullptr;
+    std::vector<qsv_gate> g2;
+    std::vector<std::vector<double>> store;
+    std::string err;
+    qsv_status rc;
+    try {
+        rc = density_gates(n, g, ng, g2, store, err);
+    } catch (const std::bad_alloc &) {
+        set_error("out of host memory while expanding the density circuit");
+        return QSV_E_NOMEM;
+    }
+    if (rc != QSV_OK) {
+        set_error("qsv_plan_density: " + err);
+        return rc;
+    }
+    return qsv_plan_blocks(opt, dt, 2 * n, g2.data(), g2.size(), plan);
+}
+
 void qsv_plan_destroy(qsv_plan *plan) { delete plan; }
 
 qsv_status qsv_plan_get_stats(const qsv_plan *plan, qsv_plan_stats *out) {
@@ -763,6 +787,46 @@ qsv_status qsv_expval(qsv_ctx *ctx, const void *state, int n, const qsv_zterm *t
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     return reduce_common(ctx, 2, state, nullptr, n, 1, terms, n_terms, out_dev, (hipStream_t)stream);
+}
+
+static qsv_status dm_reduce(qsv_ctx *ctx, int kind, const void *rho, int n,
+                            const qsv_zterm *terms, size_t nt, double *out_dev, void *stream) {
+    if (n < 1 || 2 * n > QSV_MAX_QUBITS) {
+        set_error("density matrices need n in [1, " + std::to_string(QSV_MAX_QUBITS / 2) + "]");
+        return QSV_E_INVALID;
+    }
+    qsv_status rc = check_state(ctx, rho, 2 * n);
+    if (rc != QSV_OK) return rc;
+    if (!out_dev || (nt > 0 && !terms)) {
+        set_error("NULL argument");
+        return QSV_E_INVALID;
+    }
+    if (kind == 1 && (rc = check_terms(terms, nt, n)) != QSV_OK) return rc;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int nblk = reduce_blocks(n);
+    if ((rc = ws_acquire(ctx->partials, (size_t)nblk * sizeof(double), s, "reduction workspace")) != QSV_OK)
+        return rc;
+    if (kind == 1) {
+        if ((rc = ws_acquire(ctx->terms, QSV_MAX_TERMS * sizeof(qsv_zterm), s, "observable table")) != QSV_OK)
+            return rc;
+        if ((rc = upload_terms(ctx, terms, nt, s)) != QSV_OK) return rc;
+    }
+    hipError_t e = launch_dm_reduce(ctx->dtype, kind, rho, n, (const qsv_zterm *)ctx->terms.ptr,
+                                    (int)nt, (double *)ctx->partials.ptr, nblk, out_dev, s);
+    if (e != hipSuccess) return hip_fail(e, "density reduction launch");
+    if (kind == 1 && (rc = ws_release(ctx->terms, s, "observable table")) != QSV_OK) return rc;
+    return ws_release(ctx->partials, s, "reduction workspace");
+}
+
+qsv_status qsv_dm_trace(qsv_ctx *ctx, const void *rho, int n, double *out_dev, void *stream) {
+    return dm_reduce(ctx, 0, rho, n, nullptr, 0, out_dev, stream);
+}
+
+qsv_status qsv_dm_expval(qsv_ctx *ctx, const void *rho, int n, const qsv_zterm *terms,
+                         size_t n_terms, double *out_dev, void *stream) {
+    return dm_reduce(ctx, 1, rho, n, terms, n_terms, out_dev, stream);
 }
 
 qsv_status qsv_normalize(qsv_ctx *ctx, void *state, int n, double *norm_out_dev, void *stream) {

@@ -6,6 +6,8 @@ CPU oracle take its output as their input.
 
 A gate is ``Gate(kind, qubits, params, matrix, pidx)``:
   kind    one of  h x y z s sdg t tdg rx ry rz p u3  cx cz cp swap  unitary
+          or a noise channel (density-matrix plans only): amp_damp(gamma)
+          phase_damp(lambda) depolarize(p) kraus(matrix = stack of operators)
   qubits  tuple of distinct qubit indices; qubit k is bit k of the amplitude
           index.  cx is (control, target); unitary is (q0, q1, ...) with q0 the
           least significant bit of the matrix's row/column index
@@ -130,6 +132,30 @@ def grouped_quantum_volume(n, sizes, depth, seed):
                 u = haar_su(rng, 4)
                 gates.append(Gate("unitary", (grp[perm[2 * i]], grp[perm[2 * i + 1]]), (), u))
     return gates, groups
+
+
+def noisy_density_circuit(n, layers, seed, p_depol=0.01, gamma=0.02, p_phase=0.0):
+    """U3 + CX layers (as ``u3_cx_layers``) with noise channels for the
+    density-matrix method: depolarize(p_depol) after every U3 on its qubit,
+    amp_damp(gamma) on both qubits after every CX, and phase_damp(p_phase) on every
+    qubit at the end of each layer when p_phase > 0."""
+    rng = np.random.default_rng(seed)
+    gates = []
+    for _ in range(layers):
+        for q in range(n):
+            th, ph, la = rng.uniform(0.0, TWO_PI, 3)
+            gates.append(Gate("u3", (q,), (float(th), float(ph), float(la))))
+            gates.append(Gate("depolarize", (q,), (float(p_depol),)))
+        perm = rng.permutation(n)
+        for i in range(n // 2):
+            a, b = int(perm[2 * i]), int(perm[2 * i + 1])
+            gates.append(Gate("cx", (a, b)))
+            gates.append(Gate("amp_damp", (a,), (float(gamma),)))
+            gates.append(Gate("amp_damp", (b,), (float(gamma),)))
+        if p_phase > 0:
+            for q in range(n):
+                gates.append(Gate("phase_damp", (q,), (float(p_phase),)))
+    return gates
 
 
 def ghz(n):

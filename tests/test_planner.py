@@ -247,3 +247,29 @@ def test_incremental_build_tracks_headers(tmp_path, monkeypatch):
     h.write_text("")
     os.utime(str(obj), (old + 10, old + 10))
     assert bld._stale(str(obj), str(src))
+
+
+def test_density_plan_shape_and_validation():
+    n = 5
+    gates = W.noisy_density_circuit(n, 2, 0, 0.01, 0.02, 0.01)
+    p = B.Plan.density(n, gates, B.QSV_C128, chunk_bits=8)
+    st = p.stats()
+    assert st["n"] == 2 * n and p.n == 2 * n
+    # every circuit gate twice (row and column copies), every channel once
+    nchan = sum(1 for g in gates if g[0] in ("amp_damp", "phase_damp", "depolarize"))
+    assert st["n_gates"] == 2 * (len(gates) - nchan) + nchan
+    with pytest.raises(B.QsvError) as e:      # channels need a density plan
+        B.Plan(n, gates, B.QSV_C128)
+    assert e.value.status == -4
+    with pytest.raises(B.QsvError) as e:
+        B.Plan.density(n, [("amp_damp", (0,), (1.5,), None, -1)], B.QSV_C128)
+    assert e.value.status == -1
+    with pytest.raises(B.QsvError) as e:
+        B.Plan.density(18, [], B.QSV_C128)
+    assert e.value.status == -1
+    with pytest.raises(B.QsvError) as e:
+        B.Plan.density(n, [("ry", (0,), (0.1,), None, 0)], B.QSV_C128)
+    assert e.value.status == -4
+    with pytest.raises(B.QsvError) as e:
+        B.Plan.density(n, [("depolarize", (0,), (float("nan"),), None, -1)], B.QSV_C128)
+    assert e.value.status == -5
