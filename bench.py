@@ -28,6 +28,10 @@ HBM_PEAK_GBS = 8000.0
 # MI355X vector peaks (256 CUs x 2.4 GHz): FP64 78.6 TFLOP/s; FP32 157.3 TFLOP/s,
 # of which single-issue (non-packed) FP32 reaches half
 ALU_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+# sections timed per autotune candidate (scaled by the candidate's section count),
+# then the best TUNE_REFINE estimates timed on whole applies
+TUNE_SECTIONS = 6
+TUNE_REFINE = 3
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "section_kernel_qv33_c128_traffic.json")
 
 
@@ -46,6 +50,12 @@ def parse():
     ap.add_argument("--fusion", type=int, default=None)
     ap.add_argument("--register-bits", type=int, default=None)
     ap.add_argument("--io-phases", type=int, default=None)
+    ap.add_argument("--autotune", choices=["live", "cache", "off"], default="live",
+                    help="live: tune on this workload now (the default); cache: reuse a stored "
+                         "result for the same (arch, dtype, n, circuit) if there is one; off: "
+                         "library defaults.  Explicit plan options also turn it off.")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file (default: $QSV_AUTOTUNE_CACHE or ~/.cache/qsv)")
     ap.add_argument("--workload", choices=["qv", "trajectories", "adjoint"], default="qv",
                     help="qv: the headline blocked apply (default); trajectories: 512 noisy "
                          "trajectories in one graph launch; adjoint: 20-qubit ansatz gradients")
@@ -152,6 +162,37 @@ def roofline(st, dt, B, steps, pass_bytes, achieved_gbs, avg_launch_ms, sec_ms, 
     return out
 
 
+def gpu_arch(torch):
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:  # pragma: no cover
+        return "unknown"
+
+
+def autotune(args, torch, B, dtype, n, circuit_class, run):
+    """Choose plan options with the library's autotuner.  run() -> (chosen,
+    candidates, ms).  Returns (options dict or None, record for the JSON line)."""
+    explicit = any(getattr(args, k) is not None for k in
+                   ("chunk_bits", "pinned", "fusion", "register_bits", "io_phases"))
+    if args.autotune == "off" or explicit:
+        return None, {"mode": "off" if not explicit else "explicit options"}
+    cache = B.AutotuneCache(args.tune_cache)
+    key = B.AutotuneCache.key(gpu_arch(torch), dtype, n, circuit_class)
+    t0 = time.perf_counter()
+    if args.autotune == "live":
+        chosen, cands, ms = run()
+        cache.put(key, chosen, cands, ms)
+        entry, hit = cache.get(key), False
+    else:
+        entry, hit = cache.tune(key, run)
+    tune_s = time.perf_counter() - t0
+    log("autotune %s: %s (%s, %.1f s)" % (key, entry["chosen"], "cache" if hit else "measured", tune_s))
+    rec = {"mode": args.autotune, "key": key, "cache_hit": hit, "tune_s": round(tune_s, 2),
+           "chosen": entry["chosen"],
+           "candidates": [{"options": c, "ms": m} for c, m in zip(entry["candidates"], entry["ms"])]}
+    return dict(entry["chosen"]), rec
+
+
 def timed_calls(torch, fn, steps, warmup):
     """Run fn warmup + steps times on the current stream; return the wall time
     of the timed calls (seconds) and the event time on the current stream (ms)."""
@@ -173,15 +214,25 @@ def bench_trajectories(args, torch, B, W):
     """512 Pauli-noise trajectories (10-20 qubits, depth 40, p = 1e-3),
     complex64 with FP64 renormalisation: one captured graph per call."""
     trajs = W.noisy_trajectories(512, 10, 20, 40, 1e-3, args.seed)
-    t0 = time.perf_counter()
-    plans = [B.Plan(n, g, B.QSV_C64) for n, g in trajs]
-    t_plan = time.perf_counter() - t0
     offs, o = [], 0
     for n, _ in trajs:
         offs.append(o)
         o += 1 << n
     ctx = B.Context(B.QSV_C64)
     states = torch.empty(o, dtype=torch.complex64, device="cuda")
+
+    def tune():
+        cands = B.batch_candidates(B.QSV_C64)
+        best, ms = ctx.autotune_batch(trajs, offs, states, candidates=cands, reps=2)
+        return best, cands, ms
+
+    chosen, tune_rec = autotune(args, torch, B, B.QSV_C64, 20, "512 noisy trajectories 10-20q "
+                                "depth 40 seed %d" % args.seed, tune)
+    opts = chosen or dict(chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
+                          fusion_max_qubits=args.fusion, register_bits=args.register_bits)
+    t0 = time.perf_counter()
+    plans = [B.Plan(n, g, B.QSV_C64, **opts) for n, g in trajs]
+    t_plan = time.perf_counter() - t0
     norms = torch.empty(len(trajs), dtype=torch.float64, device="cuda")
     step_bytes = sum(p.stats()["n_sections"] * 2.0 * (1 << p.n) * 8 for p in plans)
     gates = sum(len(g) for _, g in trajs)
@@ -198,7 +249,10 @@ def bench_trajectories(args, torch, B, W):
         "data": "synthetic",
         "config": {"workload": "512 trajectories, n ~ U{10..20}, depth 40 U3+CX, Pauli p=1e-3, "
                                "complex64, seed %d" % args.seed,
-                   "gates": gates, "states_mib": round(o * 8 / 2 ** 20, 1), "plan_s": round(t_plan, 3)},
+                   "gates": gates, "states_mib": round(o * 8 / 2 ** 20, 1), "plan_s": round(t_plan, 3),
+                   "chunk_bits": max(p.stats()["chunk_bits"] for p in plans),
+                   "register_bits": plans[0].stats()["register_bits"],
+                   "fusion_max_qubits": plans[0].stats()["fusion_max_qubits"]},
         "gates_per_s": round(gates * args.steps / wall, 1),
         "roofline": {"bound": "hbm", "kernel": "batch graph (k_batch_init, k_batch_step per depth, k_batch_norms, k_batch_scale)",
                      "achieved": round(step_bytes / (ev_ms / args.steps * 1e-3) / 1e9, 1),
@@ -207,6 +261,7 @@ def bench_trajectories(args, torch, B, W):
                      "traffic": None,
                      "note": "algorithmic bytes = sum over trajectories of sections x 2 x 2^n x 8 B; "
                              "states of 10-20 qubits are largely cache-resident"},
+        "autotune": tune_rec,
     }
     if not args.skip_cpu:
         import oracle
@@ -239,19 +294,27 @@ def bench_adjoint(args, torch, B, W):
     tmpl = W.hardware_efficient_ansatz(n, layers)
     theta = torch.from_numpy(W.ansatz_parameters(n, layers, batch, args.seed)).cuda()
     terms = [(1.0, (1 << i) | (1 << ((i + 1) % n))) for i in range(n)]
-    t0 = time.perf_counter()
-    # chunk 11 with 8 amplitudes per thread: psi and lambda both sit in registers
-    # during the reverse sweep, and r = 3 keeps that kernel at 3 waves per SIMD
-    # (measured: 275 ms per call against 440 ms at the forward defaults 12 / 4)
-    plan = B.Plan(n, tmpl, dt, fusion_max_qubits=2,
-                  chunk_bits=args.chunk_bits if args.chunk_bits is not None else 11,
-                  register_bits=args.register_bits if args.register_bits is not None else 3,
-                  pinned_low_bits=args.pinned)
-    t_plan = time.perf_counter() - t0
-    S = plan.stats()["n_sections"]
     ctx = B.Context(dt)
     psi = torch.empty(batch << n, dtype=tdt, device="cuda")
     lam = torch.empty_like(psi)
+
+    def tune():
+        cands = B.adjoint_candidates(dt, n)
+        best, ms = ctx.autotune_adjoint(n, tmpl, terms, theta, psi, lam, candidates=cands, reps=1)
+        return best, cands, ms
+
+    chosen, tune_rec = autotune(args, torch, B, dt, n, "hardware-efficient ansatz 40 layers "
+                                "batch %d seed %d" % (batch, args.seed), tune)
+    # without tuning: chunk 11 with 8 amplitudes per thread (psi and lambda both sit
+    # in registers during the reverse sweep; r = 3 keeps that kernel at 3 waves per SIMD)
+    opts = chosen or dict(fusion_max_qubits=2,
+                          chunk_bits=args.chunk_bits if args.chunk_bits is not None else 11,
+                          register_bits=args.register_bits if args.register_bits is not None else 3,
+                          pinned_low_bits=args.pinned)
+    t0 = time.perf_counter()
+    plan = B.Plan(n, tmpl, dt, **opts)
+    t_plan = time.perf_counter() - t0
+    S = plan.stats()["n_sections"]
     energy = torch.empty(batch, dtype=torch.float64, device="cuda")
     grad = torch.empty(batch, 2 * n * layers, dtype=torch.float64, device="cuda")
     call = lambda: ctx.adjoint_grad(plan, terms, theta, psi, lam, energy, grad)
@@ -277,6 +340,7 @@ def bench_adjoint(args, torch, B, W):
                      "frac": round(call_bytes / (ev_ms / args.steps * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "traffic": None,
                      "note": "algorithmic bytes per call = batch x (6 S + 3) x 2^n x es"},
+        "autotune": tune_rec,
     }
     if not args.skip_cpu:
         import oracle
@@ -321,10 +385,26 @@ def main():
     tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
     es = 16 if dt == B.QSV_C128 else 8
     gates = W.quantum_volume(n, n, args.seed)
+    torch.cuda.init()
+    ctx = B.Context(dt)
+    A = torch.empty(1 << n, dtype=tdt, device="cuda")
+
+    def tune():
+        cands = B.state_candidates(dt, n)
+        best, ms = ctx.autotune(n, gates, candidates=cands, reps=1, scratch=A,
+                                max_sections=TUNE_SECTIONS, refine=TUNE_REFINE)
+        return best, cands, ms
+
+    chosen, tune_rec = autotune(args, torch, B, dt, n, "quantum-volume depth %d seed %d"
+                                % (n, args.seed), tune)
+    if tune_rec.get("mode") in ("live", "cache"):
+        tune_rec["max_sections"] = TUNE_SECTIONS
+        tune_rec["refined"] = TUNE_REFINE
+    opts = chosen or dict(chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
+                          fusion_max_qubits=args.fusion, register_bits=args.register_bits,
+                          io_phases=args.io_phases)
     t0 = time.perf_counter()
-    plan = B.Plan(n, gates, dt, chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
-                  fusion_max_qubits=args.fusion, register_bits=args.register_bits,
-                  io_phases=args.io_phases)
+    plan = B.Plan(n, gates, dt, **opts)
     t_plan = time.perf_counter() - t0
     st = plan.stats()
     S = st["n_sections"]
@@ -333,9 +413,6 @@ def main():
     log("planned n=%d gates=%d sections=%d phases=%d ops=%d in %.3f s"
         % (n, len(gates), S, st["n_phases"], st["n_device_ops"], t_plan))
 
-    torch.cuda.init()
-    ctx = B.Context(dt)
-    A = torch.empty(1 << n, dtype=tdt, device="cuda")
     ctx.init_basis(A, n, 0)
     ctx.apply(plan, A)
     torch.cuda.synchronize()
@@ -452,6 +529,7 @@ def main():
         "parity": parity,
         "roofline": roofline(st, dt, B, args.steps, pass_bytes, achieved, avg_launch_ms,
                              sec_ms, sec_launches, traffic),
+        "autotune": tune_rec,
     }
     if not args.skip_cpu:
         rec["cpu_baseline"] = cpu_baseline(n, gates, step_bytes, args.seed)

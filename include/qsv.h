@@ -125,7 +125,20 @@ typedef struct {
                                     extra op-free phase in which lanes sit on those bits: one more
                                     LDS transposition for coalesced HBM access (large states
                                     only); 0: gather and scatter in the phases' own maps */
+    int32_t planner;             /* chunk choice (Sec. IV-A leaves it open; its heuristic is
+                                    not claimed optimal): QSV_PLANNER_DEFAULT (greedy
+                                    candidates scored by a greedy rollout of the rest, one
+                                    section of lookahead above 1024 gates), _GREEDY (one
+                                    section of lookahead), _BEAM (beam searches over
+                                    section sequences (one beam ranked by remaining gates, one by a greedy
+                                    rollout of the rest), never more sections than DEFAULT; remap
+                                    mode), _EXACT (minimum number of sections by breadth-first
+                                    search; remap mode, at most 64 gates and 24 qubits,
+                                    QSV_E_UNSUPPORTED beyond or when the search is too large) */
 } qsv_options;
+
+enum { QSV_PLANNER_DEFAULT = 0, QSV_PLANNER_GREEDY = 1, QSV_PLANNER_BEAM = 2,
+       QSV_PLANNER_EXACT = 3 };
 
 /* Fill *opt with the defaults for dt. */
 qsv_status qsv_default_options(qsv_dtype dt, qsv_options *opt);
@@ -321,13 +334,20 @@ qsv_status qsv_batch_run(qsv_ctx *ctx, int count, const qsv_plan *const *plans,
 /* Time `n_cands` option sets on the circuit (n, g, ng): for each, plan, run one
  * untimed blocked apply on `state` (a caller-owned scratch of 2^n amplitudes of the
  * context's dtype, overwritten), then `reps` timed applies between HIP events on
- * `stream`.  *best = index of the fastest candidate; ms_out[k] (host, may be NULL) =
- * mean milliseconds per apply, +inf for candidates that cannot be planned.  Chooses
- * chunk_bits, pinned_low_bits, fusion_max_qubits and register_bits for the caller's
- * own workload (the paper's chunk size nc, Sec. II-B, is a free parameter). */
+ * `stream`.  With max_sections > 0 a remap-mode candidate runs only its first
+ * max_sections sections (qsv_apply_sections) and its time is scaled by
+ * S / max_sections, S being that candidate's section count, so large circuits are
+ * compared without running them whole; then (refine > 0) the `refine` best estimates
+ * are timed again on whole applies and the winner is the fastest of those.
+ * *best = index of the winner; ms_out[k] (host, may be NULL) = milliseconds per whole
+ * apply (measured for refined candidates, else the estimate), +inf for candidates that
+ * cannot be planned.  Chooses chunk_bits, pinned_low_bits,
+ * fusion_max_qubits, register_bits and the schedule options (swap_mode, io_phases)
+ * for the caller's own workload (the paper's chunk size nc, Sec. II-B, is a free
+ * parameter). */
 qsv_status qsv_autotune(qsv_ctx *ctx, qsv_dtype dt, int n, const qsv_gate *g, size_t ng,
-                        const qsv_options *cands, int n_cands, void *state, int reps, void *stream,
-                        int *best, double *ms_out);
+                        const qsv_options *cands, int n_cands, void *state, int reps,
+                        int max_sections, int refine, void *stream, int *best, double *ms_out);
 /* The same for a batch of circuits run through qsv_batch_run (ns[b], gates[b], ngs[b],
  * offsets[b] as there; states / norms_dev are overwritten). */
 qsv_status qsv_autotune_batch(qsv_ctx *ctx, qsv_dtype dt, int count, const int *ns,
@@ -335,6 +355,15 @@ qsv_status qsv_autotune_batch(qsv_ctx *ctx, qsv_dtype dt, int count, const int *
                               const uint64_t *offsets, const qsv_options *cands, int n_cands,
                               void *states, double *norms_dev, int reps, void *stream, int *best,
                               double *ms_out);
+
+/* The same for qsv_adjoint_grad on a parameterised circuit: every candidate plan runs
+ * the whole forward + reverse sweep (psi_dev, lambda_dev, energy_dev, grad_dev are
+ * overwritten); candidates the adjoint sweep does not support get +inf. */
+qsv_status qsv_autotune_adjoint(qsv_ctx *ctx, qsv_dtype dt, int n, const qsv_gate *g, size_t ng,
+                                const qsv_zterm *terms, size_t n_terms, const double *params_dev,
+                                int batch, void *psi_dev, void *lambda_dev, double *energy_dev,
+                                double *grad_dev, const qsv_options *cands, int n_cands, int reps,
+                                void *stream, int *best, double *ms_out);
 
 /* ---- timing (in-library HIP events around each launch) ------------------ */
 

@@ -18,6 +18,7 @@ QSV_C64, QSV_C128 = 1, 2
 QSV_SWAP_REMAP, QSV_SWAP_MATERIALIZE = 0, 1
 QSV_MODE_BLOCKED, QSV_MODE_PER_GATE = 0, 1
 QSV_OP_BEGIN, QSV_OP_END, QSV_OP_CHUNK_SWAP, QSV_OP_GATE = 1, 2, 3, 4
+QSV_PLANNER_DEFAULT, QSV_PLANNER_GREEDY, QSV_PLANNER_BEAM, QSV_PLANNER_EXACT = 0, 1, 2, 3
 
 KINDS = {k: i + 1 for i, k in enumerate(
     ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "rx", "ry", "rz", "p", "u3",
@@ -44,7 +45,7 @@ class Options(ctypes.Structure):
     _fields_ = [("chunk_bits", ctypes.c_int32), ("pinned_low_bits", ctypes.c_int32),
                 ("fusion_max_qubits", ctypes.c_int32), ("swap_mode", ctypes.c_int32),
                 ("diag_free", ctypes.c_int32), ("register_bits", ctypes.c_int32),
-                ("io_phases", ctypes.c_int32)]
+                ("io_phases", ctypes.c_int32), ("planner", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -74,6 +75,7 @@ EXPORTED = [
     "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
     "qsv_timing_enable", "qsv_timing_read", "qsv_autotune", "qsv_autotune_batch",
     "qsv_reserve", "qsv_overlap_noalloc", "qsv_plan_density", "qsv_dm_trace", "qsv_dm_expval",
+    "qsv_autotune_adjoint",
 ]
 
 _lib = None
@@ -118,8 +120,11 @@ def lib():
         "qsv_overlap_noalloc": (I, [P, P, P, I, P, P]),
         "qsv_timing_enable": (I, [P, I]),
         "qsv_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_int64), I]),
-        "qsv_autotune": (I, [P, I, I, ctypes.POINTER(Gate), SZ, ctypes.POINTER(Options), I, P, I, P,
-                             ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "qsv_autotune": (I, [P, I, I, ctypes.POINTER(Gate), SZ, ctypes.POINTER(Options), I, P, I, I,
+                             I, P, ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "qsv_autotune_adjoint": (I, [P, I, I, ctypes.POINTER(Gate), SZ, ctypes.POINTER(ZTerm), SZ, P,
+                                     I, P, P, P, P, ctypes.POINTER(Options), I, I, P,
+                                     ctypes.POINTER(I), ctypes.POINTER(D)]),
         "qsv_autotune_batch": (I, [P, I, I, ctypes.POINTER(I), ctypes.POINTER(ctypes.POINTER(Gate)),
                                    ctypes.POINTER(SZ), ctypes.POINTER(U64), ctypes.POINTER(Options),
                                    I, P, P, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]),
@@ -512,6 +517,56 @@ def default_candidates(dtype, n):
     return out
 
 
+def state_candidates(dtype, n):
+    """Bounded grid for one large state: chunk bits c and register bits r around the
+    defaults (within the kernels' thread limits), pinned low bits L, fusion width f,
+    and the schedule options io_phases and the planner (section sequence)."""
+    base = default_options(dtype)
+    out = []
+    for dc in (-1, 0):
+        c = min(base.chunk_bits + dc, n)
+        for r in (base.register_bits - 1, base.register_bits):
+            if r < 1 or c - r > (9 if r <= 4 else 8):
+                continue
+            for L in (base.pinned_low_bits, base.pinned_low_bits + 1):
+                out.append(dict(chunk_bits=c, register_bits=r, pinned_low_bits=min(L, c - 2),
+                                fusion_max_qubits=2, io_phases=0))
+    out.append(dict(chunk_bits=min(base.chunk_bits, n), register_bits=base.register_bits,
+                    pinned_low_bits=base.pinned_low_bits, fusion_max_qubits=3, io_phases=0))
+    out.append(dict(chunk_bits=min(base.chunk_bits, n), register_bits=base.register_bits,
+                    pinned_low_bits=base.pinned_low_bits, fusion_max_qubits=2, io_phases=1))
+    # section schedule: the beam-search planner on the default shape
+    out.append(dict(chunk_bits=min(base.chunk_bits, n), register_bits=base.register_bits,
+                    pinned_low_bits=base.pinned_low_bits, fusion_max_qubits=2, io_phases=0,
+                    planner=QSV_PLANNER_BEAM))
+    return out
+
+
+def adjoint_candidates(dtype, n):
+    """Grid for the adjoint sweep: chunk and register bits (fusion of at most 2
+    qubits, which the reverse sweep requires)."""
+    out = []
+    for c in (10, 11, 12):
+        for r in (3, 4):
+            if c > n or c - r > 8 or (dtype == QSV_C128 and r > 4):
+                continue
+            out.append(dict(chunk_bits=c, register_bits=r, fusion_max_qubits=2))
+    return out
+
+
+def batch_candidates(dtype):
+    """Grid for qsv_batch_run: chunk bits, register bits and fusion width (each
+    candidate plans every trajectory and captures its own graph, so the grid is short)."""
+    if dtype == QSV_C64:
+        return [dict(chunk_bits=11, register_bits=4, fusion_max_qubits=2),
+                dict(chunk_bits=12, register_bits=4, fusion_max_qubits=2),
+                dict(chunk_bits=12, register_bits=4, fusion_max_qubits=3),
+                dict(chunk_bits=13, register_bits=5, fusion_max_qubits=2)]
+    return [dict(chunk_bits=10, register_bits=3, fusion_max_qubits=2),
+            dict(chunk_bits=11, register_bits=3, fusion_max_qubits=2),
+            dict(chunk_bits=12, register_bits=4, fusion_max_qubits=2)]
+
+
 def _options_array(dtype, cands):
     arr = (Options * len(cands))()
     for i, kw in enumerate(cands):
@@ -519,8 +574,11 @@ def _options_array(dtype, cands):
     return arr
 
 
-def _autotune(self, n, gates, candidates=None, reps=2, scratch=None, stream=None):
-    """qsv_autotune: returns (best option dict, per-candidate ms)."""
+def _autotune(self, n, gates, candidates=None, reps=2, scratch=None, stream=None, max_sections=0,
+              refine=0):
+    """qsv_autotune: returns (best option dict, per-candidate ms).  max_sections > 0
+    times only that many leading sections per candidate and scales by its section
+    count; refine > 0 re-times that many of the best estimates on whole applies."""
     torch = _torch()
     cands = candidates or default_candidates(self.dtype, n)
     arr = _options_array(self.dtype, cands)
@@ -530,7 +588,8 @@ def _autotune(self, n, gates, candidates=None, reps=2, scratch=None, stream=None
     best = ctypes.c_int()
     ms = (ctypes.c_double * len(cands))()
     _check(lib().qsv_autotune(self._h, self.dtype, n, g, len(gates), arr, len(cands), _ptr(st),
-                              int(reps), _stream(stream), ctypes.byref(best), ms))
+                              int(reps), int(max_sections), int(refine), _stream(stream),
+                              ctypes.byref(best), ms))
     del keep
     return cands[best.value], list(ms)
 
@@ -560,5 +619,82 @@ def _autotune_batch(self, circuits, offsets, states, candidates=None, reps=2, st
     return cands[best.value], list(ms)
 
 
+def _autotune_adjoint(self, n, gates, terms, params, psi, lam, candidates=None, reps=1,
+                      stream=None):
+    """qsv_autotune_adjoint: (best option dict, per-candidate ms per gradient call)."""
+    torch = _torch()
+    cands = candidates or adjoint_candidates(self.dtype, n)
+    arr = _options_array(self.dtype, cands)
+    g, keep = gates_to_c(gates)
+    batch = params.shape[0]
+    nparams = max([int(x[4]) for x in gates if len(x) > 4 and x[4] is not None] + [-1]) + 1
+    _check_f64(params, (batch, nparams), "params")
+    _check_state(psi, n, batch, dtype=self.dtype)
+    _check_state(lam, n, batch, dtype=self.dtype)
+    t = (ZTerm * len(terms))()
+    for i, (c, m) in enumerate(terms):
+        t[i].coeff = float(c)
+        t[i].zmask = int(m)
+    energy = torch.empty(batch, dtype=torch.float64, device=psi.device)
+    grad = torch.empty(batch, max(1, nparams), dtype=torch.float64, device=psi.device)
+    best = ctypes.c_int()
+    ms = (ctypes.c_double * len(cands))()
+    _check(lib().qsv_autotune_adjoint(self._h, self.dtype, n, g, len(gates), t, len(terms),
+                                      _ptr(params), int(batch), _ptr(psi), _ptr(lam), _ptr(energy),
+                                      _ptr(grad), arr, len(cands), int(reps), _stream(stream),
+                                      ctypes.byref(best), ms))
+    del keep
+    return cands[best.value], list(ms)
+
+
 Context.autotune = _autotune
 Context.autotune_batch = _autotune_batch
+Context.autotune_adjoint = _autotune_adjoint
+
+
+class AutotuneCache:
+    """Tuning results in a JSON file, keyed by (GPU architecture, dtype, n, circuit
+    class): {key: {"chosen": options, "candidates": [options...], "ms": [...]}}.
+    The file is read once and rewritten after every new entry."""
+
+    def __init__(self, path=None):
+        self.path = path or os.environ.get("QSV_AUTOTUNE_CACHE") or os.path.join(
+            os.path.expanduser("~"), ".cache", "qsv", "autotune.json")
+        self.data = {}
+        if os.path.exists(self.path):
+            import json
+            try:
+                with open(self.path) as f:
+                    self.data = json.load(f)
+            except (OSError, ValueError):
+                self.data = {}
+
+    @staticmethod
+    def key(arch, dtype, n, circuit_class):
+        return "%s|%s|n=%d|%s" % (arch, "c128" if dtype == QSV_C128 else "c64", int(n),
+                                  circuit_class)
+
+    def get(self, key):
+        return self.data.get(key)
+
+    def put(self, key, chosen, candidates, ms):
+        import json
+        self.data[key] = {"chosen": dict(chosen), "candidates": [dict(c) for c in candidates],
+                          "ms": [None if m == float("inf") else float(m) for m in ms]}
+        d = os.path.dirname(self.path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(self.data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+    def tune(self, key, run):
+        """Cached result for `key`, else run() -> (chosen, candidates, ms), stored.
+        Returns (entry, hit)."""
+        hit = self.get(key)
+        if hit is not None:
+            return hit, True
+        chosen, cands, ms = run()
+        self.put(key, chosen, cands, ms)
+        return self.get(key), False

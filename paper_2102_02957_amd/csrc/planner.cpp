@@ -24,6 +24,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <unordered_map>
 
 #include "qsv_internal.hpp"
 
@@ -41,6 +42,7 @@ void default_options(qsv_dtype dt, qsv_options &o) {
     o.diag_free = 1;
     o.register_bits = dt == QSV_C64 ? 5 : 4;
     o.io_phases = 0;
+    o.planner = QSV_PLANNER_DEFAULT;
 }
 
 // ---------------------------------------------------------------------------
@@ -200,6 +202,125 @@ int rollout_sections(const Blocker &B, std::vector<int> rem, uint64_t start, int
     return sections;
 }
 
+// Beam search over section sequences (remap semantics): every state is the
+// list of gates still to run; each state is expanded with the candidate chunk
+// sets of the greedy planner and the `width` states with the fewest remaining
+// gates survive each level.  The first level on which a state has no gate left
+// gives the plan.
+std::vector<uint64_t> beam_chunks(const Blocker &B, const std::vector<int> &rem0, uint64_t start,
+                                  int c, int n, int width, bool rollout) {
+    struct St {
+        std::vector<int> rem;
+        std::vector<uint64_t> chunks;
+        int est;                 // sections a greedy plan of the rest needs (rollout scoring)
+    };
+    std::vector<St> beam{St{rem0, {}, 0}};
+    std::vector<uint64_t> cands;
+    while (true) {
+        std::vector<St> next;
+        for (const St &s : beam) {
+            chunk_candidates(B, s.rem, start, c, n, cands);
+            for (uint64_t cand : cands) {
+                const uint64_t full = fill_low(cand, c, n);
+                St t;
+                t.rem = scan_rest(B, s.rem, full);
+                t.chunks = s.chunks;
+                t.chunks.push_back(full);
+                if (t.rem.empty()) return t.chunks;
+                bool dup = false;
+                for (const St &u : next) dup = dup || u.rem == t.rem;
+                if (dup) continue;
+                t.est = rollout ? rollout_sections(B, t.rem, start, c, n) : 0;
+                next.push_back(std::move(t));
+            }
+        }
+        std::stable_sort(next.begin(), next.end(), [](const St &a, const St &b) {
+            return a.est != b.est ? a.est < b.est : a.rem.size() < b.rem.size();
+        });
+        if ((int)next.size() > width) next.resize(width);
+        beam.swap(next);
+    }
+}
+
+// Exact minimum number of sections (remap semantics) by breadth-first search
+// over the sets of gates already run (at most 64 gates).  A section with chunk
+// set C runs every remaining gate whose needed qubits lie in C and none of
+// whose qubits is blocked by an earlier deferred gate (the scan of the
+// listing); running more gates never hurts, so each (state, C) pair has one
+// successor.  Returns false when the search would exceed `max_states`.
+bool exact_chunks(const Blocker &B, int ng, uint64_t pinned, int c, int n, size_t max_states,
+                  std::vector<uint64_t> &out) {
+    const uint64_t all = ng == 64 ? ~0ull : ((1ull << ng) - 1);
+    std::vector<uint64_t> needm(ng), qm(ng);
+    for (int i = 0; i < ng; ++i) {
+        needm[i] = need_local(B.G[i], B.diag_free);
+        qm[i] = B.G[i].qmask;
+    }
+    auto closure = [&](uint64_t done, uint64_t C) {
+        uint64_t blocked = 0;
+        for (int i = 0; i < ng; ++i) {
+            if ((done >> i) & 1) continue;
+            if (!(qm[i] & blocked) && !(needm[i] & ~C))
+                done |= 1ull << i;
+            else
+                blocked |= qm[i];
+        }
+        return done;
+    };
+    // chunk sets: every c-subset of the n qubits that holds the pinned ones
+    std::vector<uint64_t> chunks;
+    const int free_bits = n - popc(pinned);
+    const int want = c - popc(pinned);
+    if (want < 0 || free_bits > 24) return false;
+    std::vector<int> freeq;
+    for (int q = 0; q < n; ++q)
+        if (!((pinned >> q) & 1)) freeq.push_back(q);
+    for (uint64_t sub = 0; sub < (1ull << free_bits); ++sub) {
+        if (popc(sub) != std::min(want, free_bits)) continue;
+        uint64_t C = pinned;
+        for (int j = 0; j < free_bits; ++j)
+            if ((sub >> j) & 1) C |= bit(freeq[j]);
+        chunks.push_back(C);
+        if (chunks.size() > 4096) return false;
+    }
+    std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> parent;  // state -> (prev, chunk)
+    std::vector<uint64_t> frontier{0};
+    parent[0] = {0, 0};
+    if (ng == 0) return true;
+    while (!frontier.empty()) {
+        std::vector<uint64_t> next;
+        for (uint64_t s : frontier) {
+            for (uint64_t C : chunks) {
+                const uint64_t t = closure(s, C);
+                if (t == s || parent.count(t)) continue;
+                parent[t] = {s, C};
+                if (t == all) {
+                    for (uint64_t x = t; x != 0; x = parent[x].first) out.push_back(parent[x].second);
+                    std::reverse(out.begin(), out.end());
+                    return true;
+                }
+                next.push_back(t);
+                if (parent.size() > max_states) return false;
+            }
+        }
+        // keep only states no other state of the level contains (a superset of the
+        // gates run is never worse)
+        std::sort(next.begin(), next.end(), [](uint64_t a, uint64_t b) { return popc(a) > popc(b); });
+        std::vector<uint64_t> kept;
+        for (uint64_t t : next) {
+            bool dom = false;
+            for (uint64_t u : kept)
+                if ((t & u) == t) {
+                    dom = true;
+                    break;
+                }
+            if (!dom) kept.push_back(t);
+        }
+        frontier.swap(kept);
+    }
+    return false;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -317,7 +438,7 @@ static std::vector<cd> sorted_matrix(const std::vector<cd> &m, int k, const int 
 // ---------------------------------------------------------------------------
 // blocking
 
-static void block_circuit(Plan &P) {
+static bool block_circuit(Plan &P) {
     const int n = P.n;
     const int c = P.c;
     const bool diag_free = P.opt.diag_free != 0;
@@ -336,11 +457,46 @@ static void block_circuit(Plan &P) {
     // candidate is scored by the sections a greedy plan of the rest needs
     // (about a second of host time at 600 gates); larger circuits use one
     // section of lookahead.
-    const bool rollout = !materialise && P.gates.size() <= 1024;
+    const int strategy = P.opt.planner;
+    const bool rollout = !materialise && P.gates.size() <= 1024 && strategy == QSV_PLANNER_DEFAULT;
     P.sections.clear();
     P.chunk_swaps = 0;
     uint64_t prev_local_logical = 0;
     bool first = true;
+    // beam and exact strategies fix the whole sequence of chunk sets up front
+    // (remap semantics); the default and greedy planners choose section by section
+    std::vector<uint64_t> fixed;
+    if (strategy == QSV_PLANNER_BEAM || strategy == QSV_PLANNER_EXACT) {
+        if (strategy == QSV_PLANNER_EXACT) {
+            if (!exact_chunks(B, (int)P.gates.size(), pinned, c, n, 4000000, fixed)) return false;
+        } else {
+            // a beam ranked by remaining gates (width 16) and, for circuits the
+            // default planner also rolls out, one ranked by the greedy rollout of
+            // the rest (width 8); the shorter plan wins
+            fixed = beam_chunks(B, rem, pinned, c, n, 16, false);
+            if (P.gates.size() <= 1024) {
+                std::vector<uint64_t> r = beam_chunks(B, rem, pinned, c, n, 8, true);
+                if (r.size() < fixed.size()) fixed.swap(r);
+            }
+            // never worse than the default planner: its section count is the bound
+            Plan D;
+            D.n = n;
+            D.c = c;
+            D.gates = P.gates;
+            D.opt = P.opt;
+            D.opt.planner = QSV_PLANNER_DEFAULT;
+            (void)block_circuit(D);
+            if (D.sections.size() < fixed.size()) {
+                fixed.clear();
+                for (const HostSection &S : D.sections) {
+                    uint64_t m = 0;
+                    for (int ph : S.phys_local) m |= bit(ph);
+                    fixed.push_back(m);
+                }
+            }
+        }
+    }
+    size_t fixed_at = 0;
     while (!rem.empty()) {
         // candidate chunk sets; the first remaining gate is never blocked, so
         // each candidate admits it
@@ -380,6 +536,7 @@ static void block_circuit(Plan &P) {
                 best = full;
             }
         }
+        if (fixed_at < fixed.size()) best = fixed[fixed_at++];
         uint64_t local = best;  // logical qubits in the chunk
 
         HostSection S;
@@ -459,6 +616,7 @@ static void block_circuit(Plan &P) {
             iv[b] = qa;
         }
     }
+    return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -925,6 +1083,19 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         err = "io_phases must be 0 or 1";
         return QSV_E_INVALID;
     }
+    if (o.planner < QSV_PLANNER_DEFAULT || o.planner > QSV_PLANNER_EXACT) {
+        err = "planner must be one of QSV_PLANNER_DEFAULT, _GREEDY, _BEAM, _EXACT";
+        return QSV_E_INVALID;
+    }
+    if ((o.planner == QSV_PLANNER_BEAM || o.planner == QSV_PLANNER_EXACT) &&
+        o.swap_mode != QSV_SWAP_REMAP) {
+        err = "beam and exact planners need swap_mode QSV_SWAP_REMAP";
+        return QSV_E_UNSUPPORTED;
+    }
+    if (o.planner == QSV_PLANNER_EXACT && (ng > 64 || n > 24)) {
+        err = "the exact planner takes at most 64 gates and 24 qubits";
+        return QSV_E_UNSUPPORTED;
+    }
     if (o.swap_mode != QSV_SWAP_REMAP && o.swap_mode != QSV_SWAP_MATERIALIZE) {
         err = "swap_mode must be QSV_SWAP_REMAP or QSV_SWAP_MATERIALIZE";
         return QSV_E_INVALID;
@@ -977,7 +1148,11 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     // (the widest fused-op kernel instance)
     P.fusion_eff = o.fusion_max_qubits < 2 ? o.fusion_max_qubits : std::min(o.fusion_max_qubits, std::min(P.r, 4));
 
-    block_circuit(P);
+    if (!block_circuit(P)) {
+        err = "the exact planner's search exceeded its state budget (use a smaller circuit or "
+              "another planner)";
+        return QSV_E_UNSUPPORTED;
+    }
     for (size_t s = 0; s < P.sections.size(); ++s) lower_section(P, (int)s);
     lower_per_gate(P);
     P.poff.assign(P.n_params + 1, 0);

@@ -175,3 +175,8 @@ bool kind_is_diagonal(int kind);
 void set_error(const std::string &msg);
 
 }  // namespace qsv
+
+// the opaque plan handle of the C ABI
+struct qsv_plan {
+    qsv::Plan p;
+};

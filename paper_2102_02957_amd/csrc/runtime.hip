@@ -22,9 +22,6 @@
 #include "device.hpp"
 #include "qsv_internal.hpp"
 
-struct qsv_plan {
-    qsv::Plan p;
-};
 
 namespace qsv {
 

@@ -73,3 +73,53 @@ def test_autotune_batch(torch):
         want = oracle.apply_circuit(n, gates)
         assert 1.0 - oracle.fidelity(got, want) < 1e-5, b
         assert oracle.max_abs_diff(got, want) <= 2e-5 * np.max(np.abs(want)), b
+
+
+def test_autotune_section_budget(torch):
+    """With a section budget each candidate runs only its leading sections; the
+    estimates are finite and the winner's plan still matches the oracle."""
+    n = 18
+    gates = W.quantum_volume(n, n, 3)
+    ctx = B.Context(B.QSV_C64)
+    cands = [dict(chunk_bits=10, register_bits=4, pinned_low_bits=3),
+             dict(chunk_bits=11, register_bits=5, pinned_low_bits=4),
+             dict(chunk_bits=12, register_bits=5, pinned_low_bits=4, io_phases=1)]
+    best, ms = ctx.autotune(n, gates, candidates=cands, reps=1, max_sections=2)
+    assert all(math.isfinite(m) and m > 0 for m in ms)
+    assert best == cands[int(np.argmin(ms))]
+    # refine: the two best estimates are re-timed on whole applies; the winner is one of them
+    best2, ms2 = ctx.autotune(n, gates, candidates=cands, reps=1, max_sections=2, refine=2)
+    assert all(math.isfinite(m) and m > 0 for m in ms2) and best2 in cands
+    plan = B.Plan(n, gates, B.QSV_C64, **best)
+    st = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    ctx.init_basis(st, n, 0)
+    ctx.apply(plan, st)
+    got = st.cpu().numpy().astype(np.complex128)
+    want = oracle.apply_circuit(n, gates)
+    assert 1.0 - oracle.fidelity(got, want) < 1e-5
+    assert oracle.max_abs_diff(got, want) <= 2e-5 * np.max(np.abs(want))
+
+
+def test_autotune_adjoint(torch):
+    """Adjoint candidates: one the reverse sweep refuses (fusion of 3 qubits) gets
+    +inf; the winner's gradients match the oracle."""
+    n, layers, batch = 10, 3, 2
+    tmpl = W.hardware_efficient_ansatz(n, layers)
+    theta = W.ansatz_parameters(n, layers, batch, 7)
+    terms = oracle.ring_zz_terms(n)
+    ctx = B.Context(B.QSV_C128)
+    psi = torch.empty(batch << n, dtype=torch.complex128, device="cuda")
+    lam = torch.empty_like(psi)
+    th = torch.from_numpy(theta).cuda()
+    cands = [dict(chunk_bits=8, register_bits=3, fusion_max_qubits=2),
+             dict(chunk_bits=8, register_bits=4, fusion_max_qubits=3),
+             dict(chunk_bits=9, register_bits=4, fusion_max_qubits=2)]
+    best, ms = ctx.autotune_adjoint(n, tmpl, terms, th, psi, lam, candidates=cands, reps=1)
+    assert math.isinf(ms[1]) and math.isfinite(ms[0]) and math.isfinite(ms[2])
+    assert best == cands[int(np.argmin(ms))]
+    plan = B.Plan(n, tmpl, B.QSV_C128, **best)
+    e, g = ctx.adjoint_grad(plan, terms, th, psi, lam)
+    for b in range(batch):
+        ew, gw = oracle.adjoint_gradient(n, tmpl, theta[b], terms)
+        assert abs(e[b].item() - ew) < 1e-11
+        assert np.max(np.abs(g[b].cpu().numpy() - gw)) < 1e-10

@@ -352,3 +352,22 @@ def test_large_qv_vs_oracle(torch, ctxs):
     got, plan = run_gpu(torch, ctxs, n, gates, B.QSV_C128, chunk_bits=10, register_bits=4)
     assert plan.stats()["n_sections"] > 1
     assert_close(got, oracle.apply_circuit(n, gates), B.QSV_C128, "qv23")
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_beam_and_exact_planner_plans(torch, ctxs, dt):
+    """Plans of the beam-search and exact planners run on the device and match
+    the oracle (the section sequence differs, the state does not)."""
+    n = 20
+    gates = W.quantum_volume(n, n, 5)
+    psi0 = random_state(n, 5)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, planner=B.QSV_PLANNER_BEAM)
+    assert_close(got, want, dt, "beam")
+    assert plan.stats()["n_sections"] <= B.Plan(n, gates, dt).stats()["n_sections"]
+    n = 9
+    gates = W.random_circuit(n, 40, 6, max_unitary_qubits=2)
+    psi0 = random_state(n, 6)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, planner=B.QSV_PLANNER_EXACT,
+                        chunk_bits=5, register_bits=3, pinned_low_bits=1)
+    assert_close(got, oracle.apply_circuit(n, gates, psi0), dt, "exact")

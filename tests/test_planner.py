@@ -273,3 +273,113 @@ def test_density_plan_shape_and_validation():
     with pytest.raises(B.QsvError) as e:
         B.Plan.density(n, [("depolarize", (0,), (float("nan"),), None, -1)], B.QSV_C128)
     assert e.value.status == -5
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    """The JSON cache stores the chosen options and the candidate table per key,
+    survives a reload, and a hit skips the tuner."""
+    path = str(tmp_path / "sub" / "tune.json")
+    c = B.AutotuneCache(path)
+    key = B.AutotuneCache.key("gfx950", B.QSV_C64, 34, "quantum-volume")
+    calls = []
+
+    def run():
+        calls.append(1)
+        cands = [dict(chunk_bits=12), dict(chunk_bits=13)]
+        return cands[1], cands, [2.0, float("inf")]
+
+    e, hit = c.tune(key, run)
+    assert not hit and e["chosen"] == {"chunk_bits": 13} and e["ms"] == [2.0, None]
+    c2 = B.AutotuneCache(path)
+    e2, hit2 = c2.tune(key, run)
+    assert hit2 and e2 == e and len(calls) == 1
+    assert key == "gfx950|c64|n=34|quantum-volume"
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_candidate_grids_are_plannable(dt):
+    """Every candidate of the bench grids is accepted by the planner at its size."""
+    n = 22
+    g = W.quantum_volume(n, 4, 0)
+    for kw in B.state_candidates(dt, n):
+        B.Plan(n, g, dt, **kw)
+    for kw in B.adjoint_candidates(dt, 20):
+        B.Plan(20, W.hardware_efficient_ansatz(20, 2), dt, **kw)
+    for kw in B.batch_candidates(dt):
+        B.Plan(14, W.u3_cx_layers(14, 2, 0), dt, **kw)
+
+
+def brute_min_sections(n, gates, c, pinned=0):
+    """Minimum number of sections by breadth-first search over the sets of gates
+    already run, written independently of the library: a section with chunk set C
+    runs, in order, every remaining gate whose qubits lie in C and share no qubit
+    with an earlier remaining gate that did not run."""
+    from itertools import combinations
+    G = len(gates)
+    qs = [set(g[1]) for g in gates]
+    chunks = [set(C) | set(range(pinned)) for C in combinations(range(pinned, n), c - pinned)]
+    frontier, seen, depth = {frozenset()}, {frozenset()}, 0
+    while frontier:
+        depth += 1
+        nxt = set()
+        for done in frontier:
+            for C in chunks:
+                ran, blocked = set(done), set()
+                for i in range(G):
+                    if i in done:
+                        continue
+                    if not (qs[i] & blocked) and qs[i] <= C:
+                        ran.add(i)
+                    else:
+                        blocked |= qs[i]
+                ran = frozenset(ran)
+                if len(ran) == G:
+                    return depth
+                if ran not in seen:
+                    seen.add(ran)
+                    nxt.add(ran)
+        frontier = nxt
+    return 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_exact_planner_is_optimal_and_correct(seed):
+    """The exact planner's section count equals an independent brute force, is
+    never above the heuristics, and its plan equals the circuit."""
+    n, c = 6, 3
+    gates = W.random_circuit(n, 14, 100 + seed, max_unitary_qubits=2)
+    want = brute_min_sections(n, gates, c)
+    counts = {}
+    for name, pl in (("default", B.QSV_PLANNER_DEFAULT), ("greedy", B.QSV_PLANNER_GREEDY),
+                     ("beam", B.QSV_PLANNER_BEAM), ("exact", B.QSV_PLANNER_EXACT)):
+        st, _ = plan_matches_circuit(n, gates, chunk_bits=c, register_bits=2, pinned_low_bits=0,
+                                     diag_free=0, planner=pl)
+        counts[name] = st["n_sections"]
+    assert counts["exact"] == want, (counts, want)
+    assert counts["exact"] <= min(counts.values())
+    assert counts["beam"] <= counts["default"]
+
+
+@pytest.mark.parametrize("name,builder,n,c", [
+    ("qv", lambda n: W.quantum_volume(n, n, 1), 16, 6),
+    ("u3cx", lambda n: W.u3_cx_layers(n, 6, 2), 14, 5),
+    ("qft", lambda n: W.qft(n), 14, 6),
+])
+def test_beam_planner_plans_equal_circuit(name, builder, n, c):
+    gates = builder(n)
+    st, _ = plan_matches_circuit(n, gates, chunk_bits=c, register_bits=3, pinned_low_bits=1,
+                                 planner=B.QSV_PLANNER_BEAM)
+    d = B.Plan(n, gates, B.QSV_C128, chunk_bits=c, register_bits=3, pinned_low_bits=1).stats()
+    assert st["n_sections"] <= d["n_sections"]
+
+
+def test_planner_option_validation():
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(8, W.ghz(8), B.QSV_C128, planner=7)
+    assert e.value.status == -1
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(8, W.ghz(8), B.QSV_C128, planner=B.QSV_PLANNER_BEAM, swap_mode=B.QSV_SWAP_MATERIALIZE)
+    assert e.value.status == -4
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(12, W.quantum_volume(12, 12, 0), B.QSV_C128, planner=B.QSV_PLANNER_EXACT)
+    assert e.value.status == -4      # 72 gates: above the exact planner's limit
