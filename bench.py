@@ -56,7 +56,11 @@ def parse():
                          "library defaults.  Explicit plan options also turn it off.")
     ap.add_argument("--tune-cache", default=None,
                     help="autotune cache file (default: $QSV_AUTOTUNE_CACHE or ~/.cache/qsv)")
-    ap.add_argument("--workload", choices=["qv", "trajectories", "adjoint"], default="qv",
+    ap.add_argument("--hbm-budget-gib", type=float, default=48.0,
+                    help="host workload: device memory for the slice buffers")
+    ap.add_argument("--sections", type=int, default=3,
+                    help="host workload: sections timed per step")
+    ap.add_argument("--workload", choices=["qv", "trajectories", "adjoint", "host"], default="qv",
                     help="qv: the headline blocked apply (default); trajectories: 512 noisy "
                          "trajectories in one graph launch; adjoint: 20-qubit ansatz gradients")
     return ap.parse_args()
@@ -365,6 +369,69 @@ def bench_adjoint(args, torch, B, W):
     print(json.dumps(rec), flush=True)
 
 
+def bench_host(args, torch, B, W):
+    """Quantum Volume with the state in pinned host memory: every section streams the
+    state through HBM slice buffers (qsv_apply_host).  One step = `--sections`
+    sections; value = host<->device bytes (state read + written per section) / time."""
+    n = args.n
+    dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64
+    tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
+    es = 16 if dt == B.QSV_C128 else 8
+    gates = W.quantum_volume(n, n, args.seed)
+    t0 = time.perf_counter()
+    plan = B.Plan(n, gates, dt, diag_free=0)
+    t_plan = time.perf_counter() - t0
+    S = plan.stats()["n_sections"]
+    ctx = B.Context(dt)
+    t0 = time.perf_counter()
+    host = torch.zeros(1 << n, dtype=tdt, pin_memory=True)
+    host[0] = 1.0
+    log("pinned host state of %d GiB ready in %.1f s" % ((es << n) >> 30, time.perf_counter() - t0))
+    budget = int(args.hbm_budget_gib * (1 << 30))
+    K = min(args.sections, S)
+    ctx.apply_host(plan, host, budget, 0, 1)            # warm-up: the first section
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(0, reset=True)
+    t1 = time.perf_counter()
+    s0 = 1
+    for _ in range(args.steps):
+        s1 = min(S, s0 + K)
+        if s1 - s0 < K:
+            s0, s1 = 1, 1 + K
+        ctx.apply_host(plan, host, budget, s0, s1)
+        s0 = s1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    kern_ms, launches = ctx.timing_read(0, reset=True)
+    ctx.timing(False)
+    moved = 2.0 * (es << n) * K * args.steps
+    o = 1
+    while 3 * (es << (n - o)) > budget:
+        o += 1
+    rec = {
+        "metric": "host-resident blocked apply: host<->HBM GB/s (state in pinned host memory), "
+                  "%dq %s" % (n, args.dtype),
+        "value": round(moved / wall / 1e9, 2), "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": round(wall * 1e3 / args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if dt == B.QSV_C128 else "f32", "data": "synthetic",
+        "config": {"workload": "quantum-volume %dq depth %d, %s, seed %d, state in pinned host "
+                               "memory (%d GiB), %d sections per step"
+                               % (n, n, args.dtype, args.seed, (es << n) >> 30, K),
+                   "sections": S, "hbm_budget_gib": args.hbm_budget_gib, "slices_per_section": 1 << o,
+                   "plan_s": round(t_plan, 3)},
+        "per_direction_gbs": round(moved / 2 / wall / 1e9, 2),
+        "kernel_ms_per_section": round(kern_ms / max(1, launches) * (1 << o), 1),
+        "roofline": {"bound": "host-link", "achieved": round(moved / 2 / wall / 1e9, 2),
+                     "peak": 64.0, "unit": "GB/s", "frac": round(moved / 2 / wall / 1e9 / 64.0, 4),
+                     "traffic": None,
+                     "note": "per-direction host<->device bytes / time against PCIe 5.0 x16 "
+                             "(64 GB/s per direction)"},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -379,6 +446,8 @@ def main():
         return bench_trajectories(args, torch, B, W)
     if args.workload == "adjoint":
         return bench_adjoint(args, torch, B, W)
+    if args.workload == "host":
+        return bench_host(args, torch, B, W)
 
     n = args.n
     dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64

@@ -248,6 +248,30 @@ qsv_status qsv_apply_circuit(qsv_ctx *ctx, const qsv_plan *plan, void *state, in
 qsv_status qsv_apply_sections(qsv_ctx *ctx, const qsv_plan *plan, void *state, int n,
                               int64_t s0, int64_t s1, void *stream);
 
+/* Host-resident state: GPU memory as the cache of a state held in host memory (Sec.
+ * IV-C: chunks stored in CPU memory are fetched to the GPU to run a section; Sec. V-B
+ * runs 33-35 qubits on GPUs plus host memory; Sec. VI: slower storage fetched into
+ * faster memory).  `host_state` is pinned host memory (hipHostMalloc) of 2^n
+ * amplitudes, 256-byte aligned.  Sections [s0, s1) of a remap-mode plan run on slices:
+ * for section s the state is cut along the o highest bits that are not local in s
+ * (qsv_plan_stream_bits), o the smallest value for which three slice buffers of
+ * 2^(n-o) amplitudes fit in `hbm_budget` bytes of device memory; each slice is copied
+ * to the device (contiguous runs of 2^(lowest cut bit) amplitudes), runs the section
+ * kernel there and is copied back, with the copies of neighbouring slices overlapping
+ * the kernels on library streams.  All of a section's slices are back in host memory
+ * before the next section reads any.  The call is asynchronous: the copies start after
+ * the work already on `stream` and `stream` waits for the last one.  The result equals
+ * qsv_apply_sections on a device-resident state bit for bit.  Plans that read
+ * non-local qubits (diag_free gates on such qubits) are refused (plan with
+ * diag_free = 0), as are budgets that need more cut bits than some section leaves
+ * non-local (QSV_E_UNSUPPORTED). */
+qsv_status qsv_apply_host(qsv_ctx *ctx, const qsv_plan *plan, void *host_state, int n,
+                          size_t hbm_budget, int64_t s0, int64_t s1, void *stream);
+/* The cut bits of every section for o slice bits: mask_out[s] (host array of
+ * n_sections entries).  Host only.  QSV_E_UNSUPPORTED when a section has fewer than o
+ * non-local bits or slices would hold less than one chunk. */
+qsv_status qsv_plan_stream_bits(const qsv_plan *plan, int o, uint64_t *mask_out);
+
 /* Blocked apply of a parameterised plan to `batch` states stored back to back
  * (state b at states + b * 2^n amplitudes), parameters params_dev[b * P + p]
  * (device, double), P = stats.n_params. */

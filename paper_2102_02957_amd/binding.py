@@ -75,7 +75,7 @@ EXPORTED = [
     "qsv_expval", "qsv_normalize", "qsv_copy", "qsv_adjoint_grad", "qsv_batch_run",
     "qsv_timing_enable", "qsv_timing_read", "qsv_autotune", "qsv_autotune_batch",
     "qsv_reserve", "qsv_overlap_noalloc", "qsv_plan_density", "qsv_dm_trace", "qsv_dm_expval",
-    "qsv_autotune_adjoint",
+    "qsv_autotune_adjoint", "qsv_apply_host", "qsv_plan_stream_bits",
 ]
 
 _lib = None
@@ -113,6 +113,8 @@ def lib():
         "qsv_adjoint_grad": (I, [P, P, ctypes.POINTER(ZTerm), SZ, P, I, P, P, P, P, P]),
         "qsv_batch_run": (I, [P, I, ctypes.POINTER(P), ctypes.POINTER(U64), P, P, P]),
         "qsv_reserve": (I, [P, P, I, I, P]),
+        "qsv_apply_host": (I, [P, P, P, I, SZ, ctypes.c_int64, ctypes.c_int64, P]),
+        "qsv_plan_stream_bits": (I, [P, I, ctypes.POINTER(U64)]),
         "qsv_plan_density": (I, [ctypes.POINTER(Options), I, I, ctypes.POINTER(Gate), SZ,
                                  ctypes.POINTER(P)]),
         "qsv_dm_trace": (I, [P, P, I, P, P]),
@@ -232,6 +234,13 @@ class Plan:
         d["final_perm"] = [s.final_perm[q] for q in range(self.n)]
         return d
 
+    def stream_bits(self, o):
+        """qsv_plan_stream_bits: the cut bits of every section for o slice bits."""
+        S = self.stats()["n_sections"]
+        out = (ctypes.c_uint64 * S)()
+        _check(lib().qsv_plan_stream_bits(self._h, int(o), out))
+        return [int(v) for v in out]
+
     def export(self):
         """The transpiled op list in the oracle's plan format."""
         need = ctypes.c_size_t()
@@ -336,6 +345,18 @@ class Context:
         n = plan.n if plan is not None else int(n)
         _check(lib().qsv_reserve(self._h, plan.handle if plan is not None else None, n,
                                  int(batch), _stream(stream)))
+
+    def apply_host(self, plan, host_state, hbm_budget, s0=0, s1=None, stream=None):
+        """qsv_apply_host: sections [s0, s1) on a pinned host tensor (torch
+        pin_memory=True), streamed through at most `hbm_budget` bytes of HBM."""
+        torch = _torch()
+        if host_state.is_cuda or not host_state.is_contiguous() or not host_state.is_pinned():
+            raise ValueError("host_state must be a contiguous pinned host tensor")
+        if dtype_of(host_state) != self.dtype or host_state.numel() != (1 << plan.n):
+            raise ValueError("host_state must hold 2^n amplitudes of the context's dtype")
+        s1 = plan.stats()["n_sections"] if s1 is None else s1
+        _check(lib().qsv_apply_host(self._h, plan.handle, ctypes.c_void_p(host_state.data_ptr()),
+                                    plan.n, int(hbm_budget), int(s0), int(s1), _stream(stream)))
 
     def apply_params(self, plan, states, params, stream=None):
         batch = params.shape[0] if params.dim() == 2 else -1

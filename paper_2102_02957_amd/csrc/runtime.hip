@@ -59,6 +59,20 @@ struct Workspace {
     bool used = false;
 };
 
+// Host-resident states: device slice buffers, copy/compute streams and the
+// per-plan tables of sections rewritten for slices (see qsv_apply_host).
+constexpr int HOST_NBUF = 3;
+struct HostStream {
+    void *buf[HOST_NBUF] = {nullptr, nullptr, nullptr};
+    size_t buf_bytes = 0;
+    hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
+    hipEvent_t ev_in[HOST_NBUF] = {}, ev_comp[HOST_NBUF] = {}, ev_out[HOST_NBUF] = {};
+    hipEvent_t ev_start = nullptr, ev_done = nullptr;
+    uint64_t tab_uid = 0;
+    int tab_o = -1;
+    void *tab = nullptr;             // DevSection[S] rewritten for slices
+};
+
 struct Timer {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<hipEvent_t> pool;
@@ -80,6 +94,7 @@ struct qsv_ctx {
     bool timing = false;
     qsv::Timer timers[2];
     std::list<qsv::BatchEntry> batches;    // prepared batch launches, most recent first
+    qsv::HostStream host;                  // qsv_apply_host resources
     std::mutex mu;
 };
 
@@ -546,6 +561,19 @@ void qsv_destroy(qsv_ctx *ctx) {
         (void)hipDeviceSynchronize();
         for (auto &b : ctx->plans) (void)hipFree(b.block);
         for (auto &b : ctx->batches) batch_release(b.launch);
+        {
+            HostStream &h = ctx->host;
+            for (void *b : h.buf)
+                if (b) (void)hipFree(b);
+            if (h.tab) (void)hipFree(h.tab);
+            for (hipStream_t st : {h.s_in, h.s_comp, h.s_out})
+                if (st) (void)hipStreamDestroy(st);
+            for (int i = 0; i < HOST_NBUF; ++i)
+                for (hipEvent_t e : {h.ev_in[i], h.ev_comp[i], h.ev_out[i]})
+                    if (e) (void)hipEventDestroy(e);
+            if (h.ev_start) (void)hipEventDestroy(h.ev_start);
+            if (h.ev_done) (void)hipEventDestroy(h.ev_done);
+        }
         ws_free(ctx->partials);
         ws_free(ctx->ptab);
         ws_free(ctx->terms);
@@ -615,6 +643,244 @@ qsv_status qsv_apply_circuit(qsv_ctx *ctx, const qsv_plan *plan, void *state, in
         }, "per-gate launch");
         if (rc != QSV_OK) return rc;
     }
+    return QSV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The o highest physical bits that are not local in section si (0 if fewer).
+uint64_t stream_bits(const Plan &P, int si, int o) {
+    uint64_t local = 0;
+    for (int p : P.sections[si].phys_local) local |= 1ull << p;
+    uint64_t m = 0;
+    int k = 0;
+    for (int b = P.n - 1; b >= 0 && k < o; --b)
+        if (!((local >> b) & 1)) {
+            m |= 1ull << b;
+            ++k;
+        }
+    return k == o ? m : 0;
+}
+
+// position of physical bit p once the bits of O are removed from the index
+uint8_t squeeze(uint8_t p, uint64_t O) {
+    return (uint8_t)(p - __builtin_popcountll(O & ((1ull << p) - 1)));
+}
+
+// A section rewritten for one slice of the state (the amplitudes whose bits in O
+// hold fixed values), stored compactly with the O bits removed from the index.
+DevSection slice_section(const DevSection &S, uint64_t O) {
+    DevSection T = S;
+    for (uint32_t i = 0; i < S.c; ++i) {
+        T.slot_phys[i] = squeeze(S.slot_phys[i], O);
+        T.gather_phys[i] = squeeze(S.gather_phys[i], O);
+        T.scatter_phys[i] = squeeze(S.scatter_phys[i], O);
+    }
+    uint32_t t = 0;
+    for (uint32_t i = 0; i < S.n_nl; ++i)
+        if (!((O >> S.nl_phys[i]) & 1)) T.nl_phys[t++] = squeeze(S.nl_phys[i], O);
+    T.n_nl = t;
+    return T;
+}
+
+// plans whose ops read non-local qubits (diag_free) cannot run on slices
+bool reads_global_bits(const Plan &P) {
+    for (const DevOp &op : P.dops) {
+        if (op.type == OP_DIAG)
+            for (int j = 0; j < op.k; ++j)
+                if (op.a[j] >= SRC_GLOBAL) return true;
+        if (op.type == OP_CX && op.a[1] >= SRC_GLOBAL) return true;
+        if (op.type == OP_PDIAG && op.a[0] >= SRC_GLOBAL) return true;
+    }
+    return false;
+}
+
+qsv_status host_setup(qsv_ctx *ctx, size_t buf_bytes) {
+    HostStream &h = ctx->host;
+    hipError_t e = hipSuccess;
+    if (!h.s_in) {
+        for (hipStream_t *st : {&h.s_in, &h.s_comp, &h.s_out})
+            if ((e = hipStreamCreateWithFlags(st, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "host streaming: stream creation");
+        for (int i = 0; i < HOST_NBUF; ++i)
+            for (hipEvent_t *ev : {&h.ev_in[i], &h.ev_comp[i], &h.ev_out[i]})
+                if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
+                    return hip_fail(e, "host streaming: event creation");
+        if ((e = hipEventCreateWithFlags(&h.ev_start, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&h.ev_done, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "host streaming: event creation");
+    }
+    if (h.buf_bytes < buf_bytes) {
+        if ((e = hipStreamSynchronize(h.s_out)) != hipSuccess) return hip_fail(e, "host streaming");
+        for (void *&b : h.buf) {
+            if (b) (void)hipFree(b);
+            b = nullptr;
+        }
+        h.buf_bytes = 0;
+        for (void *&b : h.buf)
+            if ((e = hipMalloc(&b, buf_bytes)) != hipSuccess) {
+                set_error(std::string("host streaming: slice buffer: ") + hipGetErrorString(e));
+                return QSV_E_NOMEM;
+            }
+        h.buf_bytes = buf_bytes;
+    }
+    return QSV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+qsv_status qsv_plan_stream_bits(const qsv_plan *plan, int o, uint64_t *mask_out) {
+    if (!plan || !mask_out || o < 1 || o > 30) {
+        set_error("qsv_plan_stream_bits: bad argument");
+        return QSV_E_INVALID;
+    }
+    const Plan &P = plan->p;
+    for (size_t si = 0; si < P.sections.size(); ++si) {
+        mask_out[si] = stream_bits(P, (int)si, o);
+        if (!mask_out[si] || P.n - o < (int)P.dsec[si].c) {
+            set_error("section " + std::to_string(si) + " has fewer than " + std::to_string(o) +
+                      " non-local bits to slice on");
+            return QSV_E_UNSUPPORTED;
+        }
+    }
+    return QSV_OK;
+}
+
+qsv_status qsv_apply_host(qsv_ctx *ctx, const qsv_plan *plan, void *host_state, int n,
+                          size_t hbm_budget, int64_t s0, int64_t s1, void *stream) {
+    if (!ctx || !plan || !host_state) {
+        set_error("qsv_apply_host: NULL argument");
+        return QSV_E_INVALID;
+    }
+    qsv_status rc = check_plan(ctx, plan, n);
+    if (rc != QSV_OK) return rc;
+    const Plan &P = plan->p;
+    if (((uintptr_t)host_state) % 256 != 0) {
+        set_error("host state must be 256-byte aligned");
+        return QSV_E_INVALID;
+    }
+    if (P.opt.swap_mode != QSV_SWAP_REMAP || P.n_params > 0) {
+        set_error("qsv_apply_host needs a remap-mode plan without bound parameters");
+        return QSV_E_UNSUPPORTED;
+    }
+    if (reads_global_bits(P)) {
+        set_error("qsv_apply_host: the plan reads non-local qubits (plan with diag_free = 0)");
+        return QSV_E_UNSUPPORTED;
+    }
+    if (s0 < 0 || s1 < s0 || s1 > (int64_t)P.sections.size()) {
+        set_error("section range out of bounds");
+        return QSV_E_INVALID;
+    }
+    const size_t es = amp_bytes(ctx->dtype);
+    // slices: 2^o of 2^(n-o) amplitudes; HOST_NBUF of them fit the budget
+    int o = 1;
+    while (o < n && (size_t)HOST_NBUF * ((size_t(1) << (n - o)) * es) > hbm_budget) ++o;
+    std::vector<uint64_t> omask(P.sections.size());
+    if ((rc = qsv_plan_stream_bits(plan, o, omask.data())) != QSV_OK) {
+        set_error(std::string("qsv_apply_host: HBM budget too small for this plan: ") + qsv_last_error());
+        return QSV_E_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t caller = (hipStream_t)stream;
+    const size_t slice_amps = size_t(1) << (n - o);
+    if ((rc = host_setup(ctx, slice_amps * es)) != QSV_OK) return rc;
+    const DevPlanView *pv = nullptr;
+    if ((rc = upload_plan(ctx, P, &pv)) != QSV_OK) return rc;
+    HostStream &h = ctx->host;
+    hipError_t e = hipSuccess;
+    if (h.tab_uid != P.uid || h.tab_o != o) {
+        if ((e = hipStreamSynchronize(h.s_comp)) != hipSuccess) return hip_fail(e, "host streaming");
+        if (h.tab) (void)hipFree(h.tab);
+        h.tab = nullptr;
+        h.tab_uid = 0;
+        std::vector<DevSection> T(P.dsec.size());
+        for (size_t si = 0; si < T.size(); ++si) T[si] = slice_section(P.dsec[si], omask[si]);
+        if ((e = hipMalloc(&h.tab, T.size() * sizeof(DevSection))) != hipSuccess) {
+            h.tab = nullptr;
+            set_error("host streaming: section table allocation");
+            return QSV_E_NOMEM;
+        }
+        if ((e = hipMemcpy(h.tab, T.data(), T.size() * sizeof(DevSection), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "host streaming: section table upload");
+        h.tab_uid = P.uid;
+        h.tab_o = o;
+    }
+    DevPlanView sv = *pv;
+    sv.secs = (const DevSection *)h.tab;
+    // the state is the caller's until its stream reaches this point, and the slice
+    // buffers are free once the previous call's copies back have finished
+    if ((e = hipEventRecord(h.ev_start, caller)) != hipSuccess ||
+        (e = hipStreamWaitEvent(h.s_in, h.ev_start, 0)) != hipSuccess ||
+        (e = hipStreamWaitEvent(h.s_in, h.ev_done, 0)) != hipSuccess)
+        return hip_fail(e, "host streaming: ordering");
+    char *host = (char *)host_state;
+    int64_t k_all = 0;
+    for (int64_t si = s0; si < s1; ++si) {
+        const uint64_t O = omask[si];
+        const int minO = __builtin_ctzll(O);
+        const size_t run = (size_t(1) << minO) * es;             // bytes per contiguous run
+        std::vector<int> upper;                                   // free bits above min O
+        for (int b = minO + 1; b < n; ++b)
+            if (!((O >> b) & 1)) upper.push_back(b);
+        const uint64_t nruns = 1ull << upper.size();
+        std::vector<int> obits;
+        for (int b = 0; b < n; ++b)
+            if ((O >> b) & 1) obits.push_back(b);
+        const size_t lds = section_lds(P, (int)si);
+        const bool dense_only = (P.dsec[si].flags & SEC_DENSE_ONLY) != 0;
+        for (uint64_t k = 0; k < (1ull << o); ++k, ++k_all) {
+            const int b = (int)(k_all % HOST_NBUF);
+            uint64_t fixed = 0;
+            for (int j = 0; j < o; ++j)
+                if ((k >> j) & 1) fixed |= 1ull << obits[j];
+            // the buffer is free once its previous slice went back to the host
+            if (k_all >= HOST_NBUF && (e = hipStreamWaitEvent(h.s_in, h.ev_out[b], 0)) != hipSuccess)
+                return hip_fail(e, "host streaming: ordering");
+            char *dev = (char *)h.buf[b];
+            for (uint64_t j = 0; j < nruns; ++j) {
+                uint64_t x = fixed;
+                for (size_t t = 0; t < upper.size(); ++t)
+                    if ((j >> t) & 1) x |= 1ull << upper[t];
+                if ((e = hipMemcpyAsync(dev + j * run, host + x * es, run, hipMemcpyHostToDevice,
+                                        h.s_in)) != hipSuccess)
+                    return hip_fail(e, "host streaming: copy to device");
+            }
+            if ((e = hipEventRecord(h.ev_in[b], h.s_in)) != hipSuccess ||
+                (e = hipStreamWaitEvent(h.s_comp, h.ev_in[b], 0)) != hipSuccess)
+                return hip_fail(e, "host streaming: ordering");
+            rc = timed(ctx, 0, h.s_comp, [&] {
+                return launch_section(P.dtype, P.r, P.kmax, dense_only, dev, n - o, 1, sv, (int)si,
+                                      P.c, lds, nullptr, 0, h.s_comp);
+            }, "section launch");
+            if (rc != QSV_OK) return rc;
+            if ((e = hipEventRecord(h.ev_comp[b], h.s_comp)) != hipSuccess ||
+                (e = hipStreamWaitEvent(h.s_out, h.ev_comp[b], 0)) != hipSuccess)
+                return hip_fail(e, "host streaming: ordering");
+            for (uint64_t j = 0; j < nruns; ++j) {
+                uint64_t x = fixed;
+                for (size_t t = 0; t < upper.size(); ++t)
+                    if ((j >> t) & 1) x |= 1ull << upper[t];
+                if ((e = hipMemcpyAsync(host + x * es, dev + j * run, run, hipMemcpyDeviceToHost,
+                                        h.s_out)) != hipSuccess)
+                    return hip_fail(e, "host streaming: copy to host");
+            }
+            if ((e = hipEventRecord(h.ev_out[b], h.s_out)) != hipSuccess)
+                return hip_fail(e, "host streaming: ordering");
+        }
+        // the next section's slices cut the state along other bits: every slice of
+        // this one is back in host memory before the next section reads any
+        if ((e = hipEventRecord(h.ev_done, h.s_out)) != hipSuccess ||
+            (e = hipStreamWaitEvent(h.s_in, h.ev_done, 0)) != hipSuccess)
+            return hip_fail(e, "host streaming: ordering");
+    }
+    if ((e = hipEventRecord(h.ev_done, h.s_out)) != hipSuccess ||
+        (e = hipStreamWaitEvent(caller, h.ev_done, 0)) != hipSuccess)
+        return hip_fail(e, "host streaming: ordering");
     return QSV_OK;
 }
 

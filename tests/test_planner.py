@@ -383,3 +383,21 @@ def test_planner_option_validation():
     with pytest.raises(B.QsvError) as e:
         B.Plan(12, W.quantum_volume(12, 12, 0), B.QSV_C128, planner=B.QSV_PLANNER_EXACT)
     assert e.value.status == -4      # 72 gates: above the exact planner's limit
+
+
+def test_host_stream_schedule():
+    """The cut bits of every section: o bits, none local in the section, the
+    highest non-local ones; a budget needing more cut bits than a section leaves
+    non-local is refused."""
+    n, c, o = 20, 12, 3
+    p = B.Plan(n, W.quantum_volume(n, n, 2), B.QSV_C128, chunk_bits=c, diag_free=0)
+    masks = p.stream_bits(o)
+    begins = [op[1] for op in p.export() if op[0] == "begin"]
+    assert len(masks) == len(begins) == p.stats()["n_sections"]
+    for m, local in zip(masks, begins):
+        assert bin(m).count("1") == o and m & local == 0
+        nonlocal_bits = [b for b in range(n) if not (local >> b) & 1]
+        assert sorted(b for b in range(n) if (m >> b) & 1) == nonlocal_bits[-o:]
+    with pytest.raises(B.QsvError) as e:
+        p.stream_bits(n - c + 1)
+    assert e.value.status == -4
