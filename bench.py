@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--fusion", type=int, default=None)
     ap.add_argument("--register-bits", type=int, default=None)
     ap.add_argument("--io-phases", type=int, default=None)
+    ap.add_argument("--section-kernel", type=int, default=None,
+                    help="0: register-phase kernel, 1: LDS-resident chunk")
+    ap.add_argument("--planner", type=int, default=None,
+                    help="0 default, 1 greedy, 2 beam search")
     ap.add_argument("--autotune", choices=["live", "cache", "off"], default="live",
                     help="live: tune on this workload now (the default); cache: reuse a stored "
                          "result for the same (arch, dtype, n, circuit) if there is one; off: "
@@ -177,7 +181,8 @@ def autotune(args, torch, B, dtype, n, circuit_class, run):
     """Choose plan options with the library's autotuner.  run() -> (chosen,
     candidates, ms).  Returns (options dict or None, record for the JSON line)."""
     explicit = any(getattr(args, k) is not None for k in
-                   ("chunk_bits", "pinned", "fusion", "register_bits", "io_phases"))
+                   ("chunk_bits", "pinned", "fusion", "register_bits", "io_phases",
+                    "section_kernel", "planner"))
     if args.autotune == "off" or explicit:
         return None, {"mode": "off" if not explicit else "explicit options"}
     cache = B.AutotuneCache(args.tune_cache)
@@ -471,7 +476,8 @@ def main():
         tune_rec["refined"] = TUNE_REFINE
     opts = chosen or dict(chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
                           fusion_max_qubits=args.fusion, register_bits=args.register_bits,
-                          io_phases=args.io_phases)
+                          io_phases=args.io_phases, section_kernel=args.section_kernel,
+                          planner=args.planner)
     t0 = time.perf_counter()
     plan = B.Plan(n, gates, dt, **opts)
     t_plan = time.perf_counter() - t0
@@ -584,6 +590,8 @@ def main():
             "register_bits": st["register_bits"],
             "pinned_low_bits": st["pinned_low_bits"],
             "fusion_max_qubits": st["fusion_max_qubits"],
+            "section_kernel": "lds" if opts.get("section_kernel") == 1 else "registers",
+            "planner": {None: "default", 0: "default", 1: "greedy", 2: "beam"}.get(opts.get("planner"), "default"),
             "phases": st["n_phases"],
             "plan_s": round(t_plan, 4),
         },

@@ -135,8 +135,21 @@ typedef struct {
                                     mode), _EXACT (minimum number of sections by breadth-first
                                     search; remap mode, at most 64 gates and 24 qubits,
                                     QSV_E_UNSUPPORTED beyond or when the search is too large) */
+    int32_t section_kernel;      /* QSV_KERNEL_REGISTERS: the chunk lives in registers (2^r
+                                    amplitudes per thread) and moves between register phases
+                                    through LDS; QSV_KERNEL_LDS: the chunk stays in LDS for the
+                                    whole section (2^c amplitudes of LDS per workgroup, at most
+                                    128 KiB) and every op reads and writes it there (one phase per
+                                    section; register_bits is ignored; plans without bound
+                                    parameters, not for qsv_batch_run); QSV_KERNEL_PAIRED: a
+                                    section whose gates are all dense 2-qubit gates on chunk
+                                    qubits runs phases of two fused gate pairs at fixed register
+                                    positions (the amplitudes are updated in place, no run-time
+                                    choice of registers); other sections use the register
+                                    phases; the plan uses 4 register bits */
 } qsv_options;
 
+enum { QSV_KERNEL_REGISTERS = 0, QSV_KERNEL_LDS = 1, QSV_KERNEL_PAIRED = 2 };
 enum { QSV_PLANNER_DEFAULT = 0, QSV_PLANNER_GREEDY = 1, QSV_PLANNER_BEAM = 2,
        QSV_PLANNER_EXACT = 3 };
 

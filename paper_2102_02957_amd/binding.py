@@ -19,6 +19,7 @@ QSV_SWAP_REMAP, QSV_SWAP_MATERIALIZE = 0, 1
 QSV_MODE_BLOCKED, QSV_MODE_PER_GATE = 0, 1
 QSV_OP_BEGIN, QSV_OP_END, QSV_OP_CHUNK_SWAP, QSV_OP_GATE = 1, 2, 3, 4
 QSV_PLANNER_DEFAULT, QSV_PLANNER_GREEDY, QSV_PLANNER_BEAM, QSV_PLANNER_EXACT = 0, 1, 2, 3
+QSV_KERNEL_REGISTERS, QSV_KERNEL_LDS, QSV_KERNEL_PAIRED = 0, 1, 2
 
 KINDS = {k: i + 1 for i, k in enumerate(
     ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "rx", "ry", "rz", "p", "u3",
@@ -45,7 +46,8 @@ class Options(ctypes.Structure):
     _fields_ = [("chunk_bits", ctypes.c_int32), ("pinned_low_bits", ctypes.c_int32),
                 ("fusion_max_qubits", ctypes.c_int32), ("swap_mode", ctypes.c_int32),
                 ("diag_free", ctypes.c_int32), ("register_bits", ctypes.c_int32),
-                ("io_phases", ctypes.c_int32), ("planner", ctypes.c_int32)]
+                ("io_phases", ctypes.c_int32), ("planner", ctypes.c_int32),
+                ("section_kernel", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -560,6 +562,12 @@ def state_candidates(dtype, n):
     out.append(dict(chunk_bits=min(base.chunk_bits, n), register_bits=base.register_bits,
                     pinned_low_bits=base.pinned_low_bits, fusion_max_qubits=2, io_phases=0,
                     planner=QSV_PLANNER_BEAM))
+    # paired phases (fixed register positions), default and beam planners
+    for c in sorted({min(base.chunk_bits, n), min(base.chunk_bits - 1, n)}):
+        for pl in (QSV_PLANNER_DEFAULT, QSV_PLANNER_BEAM):
+            out.append(dict(chunk_bits=c, register_bits=4, pinned_low_bits=min(3, c - 4),
+                            fusion_max_qubits=2, io_phases=0, planner=pl,
+                            section_kernel=QSV_KERNEL_PAIRED))
     return out
 
 

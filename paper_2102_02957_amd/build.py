@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libqsv.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["gates.cpp", "planner.cpp", "density.cpp", "runtime.hip", "section_kernel.hip", "section_c128.hip", "section_c64.hip",
+SOURCES = ["gates.cpp", "planner.cpp", "density.cpp", "runtime.hip", "section_kernel.hip", "section_c128.hip", "section_c64.hip", "section_lds.hip", "section_paired.hip",
            "pergate_kernels.hip", "misc_kernels.hip", "batch.hip", "adjoint.hip", "autotune.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

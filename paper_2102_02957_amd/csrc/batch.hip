@@ -202,8 +202,10 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
             err = "all plans of a batch must use the same register_bits";
             return QSV_E_UNSUPPORTED;
         }
-        if (P.n_params > 0 || P.opt.swap_mode != QSV_SWAP_REMAP) {
-            err = "batch plans must be remap-mode plans without parameters";
+        if (P.n_params > 0 || P.opt.swap_mode != QSV_SWAP_REMAP ||
+            P.opt.section_kernel == QSV_KERNEL_LDS) {
+            // paired tables are ordinary register phases (dense ops at fixed positions)
+            err = "batch plans must be remap-mode register-phase plans without parameters";
             return QSV_E_UNSUPPORTED;
         }
         if (P.c - r > 8) {

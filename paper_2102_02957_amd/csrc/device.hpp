@@ -37,6 +37,14 @@ struct DevPlanView {           // device pointers of one uploaded plan
 hipError_t launch_section(qsv_dtype dt, int r, int kmax, bool dense_only, void *state, int n,
                           int batch, DevPlanView pv, int sec, int c, size_t lds_bytes,
                           const void *ptab, int nslots, hipStream_t s);
+// One paired section (SEC_PAIRED): 2^(c-4) threads per chunk, lds_bytes as for
+// launch_section (0 for a single phase).
+hipError_t launch_section_paired(qsv_dtype dt, void *state, int n, int batch, DevPlanView pv,
+                                 int sec, int c, size_t lds_bytes, hipStream_t s);
+// One section with the chunk resident in LDS (plans with section_kernel = QSV_KERNEL_LDS:
+// one phase per section, op positions = LDS index bits).
+hipError_t launch_section_lds(qsv_dtype dt, int kmax, void *state, int n, int batch, DevPlanView pv,
+                              int sec, int c, hipStream_t s);
 // ptab[b][2 i], ptab[b][2 i + 1] for every parameterised op i (see OP_PROT / OP_PDIAG)
 hipError_t launch_param_table(qsv_dtype dt, const double *params, int n_params,
                               const PSlot *slots, int nslots, int batch, void *ptab, hipStream_t s);

@@ -1001,6 +1001,141 @@ static void lower_section(Plan &P, int si) {
 }
 
 // ---------------------------------------------------------------------------
+// paired phases: a section whose gates are all dense 2-qubit gates on local
+// qubits runs phases of exactly two ops at fixed register positions, ops[2p] on
+// positions (0, 1) and ops[2p + 1] on (2, 3) (the identity when a phase has only
+// one gate pair).  Gates on the same pair fuse into one 4 x 4 matrix.  Fixed
+// positions let the kernel update the amplitudes in place with no run-time
+// choice of registers; all relabelling happens in the LDS transpositions.
+
+// 4 x 4 matrix of a 2-qubit gate in the order (x0, x1) of the pair it acts on
+static std::vector<cd> pair_matrix(const GateRec &g, int x0) {
+    if (g.q[0] == x0) return g.m;
+    std::vector<cd> m(16);
+    auto sw = [](int i) { return ((i & 1) << 1) | ((i >> 1) & 1); };
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) m[r * 4 + c] = g.m[sw(r) * 4 + sw(c)];
+    return m;
+}
+
+static bool paired_eligible(const Plan &P, const HostSection &S) {
+    if (S.gates.empty()) return false;
+    for (int gi : S.gates) {
+        const GateRec &g = P.gates[gi];
+        if (g.nq != 2 || g.is_swap || g.param >= 0) return false;
+        if (need_local(g, P.opt.diag_free != 0) != g.qmask) return false;
+    }
+    return true;
+}
+
+static void lower_section_paired(Plan &P, int si) {
+    HostSection &S = P.sections[si];
+    const int C = (int)S.phys_local.size();
+    const int n = P.n;
+    const std::vector<int> &layout = S.layout_at;
+    std::vector<int> slot(n, -1);
+    for (int q = 0; q < n; ++q) {
+        auto it = std::find(S.phys_local.begin(), S.phys_local.end(), layout[q]);
+        if (it != S.phys_local.end()) slot[q] = (int)(it - S.phys_local.begin());
+    }
+    std::vector<int> slot_q(C);
+    for (int q = 0; q < n; ++q)
+        if (slot[q] >= 0) slot_q[slot[q]] = q;
+
+    DevSection ds;
+    std::memset(&ds, 0, sizeof(ds));
+    for (int s2 = 0; s2 < C; ++s2) ds.slot_phys[s2] = (uint8_t)S.phys_local[s2];
+    {
+        int t = 0;
+        for (int p = 0; p < n; ++p)
+            if (std::find(S.phys_local.begin(), S.phys_local.end(), p) == S.phys_local.end())
+                ds.nl_phys[t++] = (uint8_t)p;
+        ds.n_nl = (uint32_t)t;
+    }
+    ds.c = (uint32_t)C;
+    ds.phase_begin = (uint32_t)P.dphase.size();
+    ds.param_slot = (uint32_t)P.n_param_ops;
+
+    std::vector<cd> ident(16, cd(0, 0));
+    for (int i = 0; i < 4; ++i) ident[i * 5] = 1.0;
+    auto push_op = [&](int p0, const std::vector<cd> &m, bool real_op) {
+        DevOp op;
+        std::memset(&op, 0, sizeof(op));
+        op.type = OP_DENSE;
+        op.k = 2;
+        op.a[0] = (uint8_t)p0;
+        op.a[1] = (uint8_t)(p0 + 1);
+        op.slot = -1;
+        op.arg = (int32_t)P.dmats.size();
+        P.dmats.insert(P.dmats.end(), m.begin(), m.end());
+        P.dops.push_back(op);
+        if (real_op) P.flops += 32.0 * std::ldexp(1.0, n);
+    };
+
+    std::vector<int> rem = S.gates;
+    while (!rem.empty()) {
+        const GateRec &g0 = P.gates[rem[0]];
+        const int a0 = g0.q[0], a1 = g0.q[1];
+        const uint64_t maskA = g0.qmask;
+        std::vector<cd> mA = g0.m, mB = ident;
+        int b0 = -1, b1 = -1;
+        uint64_t maskB = 0, blocked = 0;
+        std::vector<int> next;
+        for (size_t t = 1; t < rem.size(); ++t) {
+            const GateRec &g = P.gates[rem[t]];
+            if (g.qmask & blocked) {
+                blocked |= g.qmask;
+                next.push_back(rem[t]);
+            } else if (g.qmask == maskA) {
+                mA = matmul(pair_matrix(g, a0), mA, 4);
+            } else if (!maskB && !(g.qmask & maskA)) {
+                b0 = g.q[0];
+                b1 = g.q[1];
+                maskB = g.qmask;
+                mB = g.m;
+            } else if (maskB && g.qmask == maskB) {
+                mB = matmul(pair_matrix(g, b0), mB, 4);
+            } else {
+                blocked |= g.qmask;
+                next.push_back(rem[t]);
+            }
+        }
+        // register positions: (a0, a1, b0, b1), filled from the highest slots when
+        // the phase has one pair; then the other local qubits by ascending slot
+        std::vector<int> regq = {a0, a1};
+        if (maskB) {
+            regq.push_back(b0);
+            regq.push_back(b1);
+        } else {
+            for (int s2 = C - 1; s2 >= 0 && (int)regq.size() < 4; --s2)
+                if (slot_q[s2] != a0 && slot_q[s2] != a1) regq.push_back(slot_q[s2]);
+        }
+        DevPhase ph;
+        std::memset(&ph, 0, sizeof(ph));
+        int p = 0;
+        for (int q : regq) ph.rd[p++] = (uint8_t)slot[q];
+        for (int s2 = 0; s2 < C; ++s2)
+            if (std::find(regq.begin(), regq.end(), slot_q[s2]) == regq.end()) ph.rd[p++] = (uint8_t)s2;
+        std::memcpy(ph.wr, ph.rd, sizeof(ph.rd));
+        ph.op_begin = (uint32_t)P.dops.size();
+        push_op(0, mA, true);
+        push_op(2, mB, maskB != 0);
+        ph.op_end = (uint32_t)P.dops.size();
+        P.dphase.push_back(ph);
+        rem.swap(next);
+    }
+    P.kmax = std::max(P.kmax, 2);
+    ds.phase_end = (uint32_t)P.dphase.size();
+    ds.flags = SEC_DENSE_ONLY | SEC_PAIRED;
+    const DevPhase &f = P.dphase[ds.phase_begin], &l = P.dphase[ds.phase_end - 1];
+    for (int q = 0; q < C; ++q) {
+        ds.gather_phys[q] = ds.slot_phys[f.rd[q]];
+        ds.scatter_phys[q] = ds.slot_phys[l.wr[q]];
+    }
+    P.dsec.push_back(ds);
+}
+
+// ---------------------------------------------------------------------------
 // per-gate op list
 
 static void lower_per_gate(Plan &P) {
@@ -1083,6 +1218,11 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         err = "io_phases must be 0 or 1";
         return QSV_E_INVALID;
     }
+    if (o.section_kernel != QSV_KERNEL_REGISTERS && o.section_kernel != QSV_KERNEL_LDS &&
+        o.section_kernel != QSV_KERNEL_PAIRED) {
+        err = "section_kernel must be QSV_KERNEL_REGISTERS, _LDS or _PAIRED";
+        return QSV_E_INVALID;
+    }
     if (o.planner < QSV_PLANNER_DEFAULT || o.planner > QSV_PLANNER_EXACT) {
         err = "planner must be one of QSV_PLANNER_DEFAULT, _GREEDY, _BEAM, _EXACT";
         return QSV_E_INVALID;
@@ -1126,7 +1266,31 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         err = "a gate acts on more qubits than the chunk holds";
         return QSV_E_INVALID;
     }
-    if (P.c - P.r > (P.r <= 4 ? 9 : 8)) {
+    if (o.section_kernel == QSV_KERNEL_LDS) {
+        // the whole chunk is one register phase: op positions are LDS index bits
+        if (P.n_params > 0) {
+            err = "the LDS-resident section kernel takes no bound parameters";
+            return QSV_E_UNSUPPORTED;
+        }
+        if (maxk > 4) {
+            err = "the LDS-resident section kernel applies dense gates of at most 4 qubits";
+            return QSV_E_UNSUPPORTED;
+        }
+        if (n - P.c + std::min(P.c, 9) > 31) {
+            err = "n - chunk_bits too large for the LDS-resident kernel's launch grid";
+            return QSV_E_UNSUPPORTED;
+        }
+        P.r = P.c;
+    }
+    if (o.section_kernel == QSV_KERNEL_PAIRED) {
+        // paired phases hold two gate pairs in registers: 4 register bits
+        if (P.c < 4 || maxk > 4) {
+            err = "paired phases need chunk_bits >= 4 and gates of at most 4 qubits";
+            return QSV_E_UNSUPPORTED;
+        }
+        P.r = 4;
+    }
+    if (o.section_kernel != QSV_KERNEL_LDS && P.c - P.r > (P.r <= 4 ? 9 : 8)) {
         err = "chunk_bits - register_bits must be <= 9 for register_bits <= 4 and <= 8 for "
               "register_bits = 5 (512 / 256 threads per workgroup)";
         return QSV_E_INVALID;
@@ -1147,13 +1311,19 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     // fused ops run in one thread's registers: at most r qubits, and at most 4
     // (the widest fused-op kernel instance)
     P.fusion_eff = o.fusion_max_qubits < 2 ? o.fusion_max_qubits : std::min(o.fusion_max_qubits, std::min(P.r, 4));
+    if (o.section_kernel == QSV_KERNEL_LDS) o.io_phases = 0, P.opt.io_phases = 0;
 
     if (!block_circuit(P)) {
         err = "the exact planner's search exceeded its state budget (use a smaller circuit or "
               "another planner)";
         return QSV_E_UNSUPPORTED;
     }
-    for (size_t s = 0; s < P.sections.size(); ++s) lower_section(P, (int)s);
+    for (size_t s = 0; s < P.sections.size(); ++s) {
+        if (o.section_kernel == QSV_KERNEL_PAIRED && paired_eligible(P, P.sections[s]))
+            lower_section_paired(P, (int)s);
+        else
+            lower_section(P, (int)s);
+    }
     lower_per_gate(P);
     P.poff.assign(P.n_params + 1, 0);
     for (const PSlot &ps : P.pslots) P.poff[ps.param + 1]++;

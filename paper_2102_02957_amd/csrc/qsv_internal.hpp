@@ -84,6 +84,9 @@ constexpr uint32_t SEC_DENSE_ONLY = 1;
 // a transposition in between, a workgroup barrier must separate every wave's
 // gather from any wave's scatter (the update is in place)
 constexpr uint32_t SEC_SYNC_SCATTER = 2;
+// paired phases: every phase is ops[2p] on register positions (0, 1) and
+// ops[2p + 1] on (2, 3), dense 4 x 4 (4 register bits)
+constexpr uint32_t SEC_PAIRED = 4;
 static_assert(sizeof(DevSection) == 128, "DevSection layout");
 
 // one parameterised op: which parameter drives it and how

@@ -595,6 +595,32 @@ __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
     if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
 }
 
+// One chunk of a paired section: every phase applies ops[2p] on register
+// positions (0, 1) and ops[2p + 1] on (2, 3).  The positions are fixed, so the
+// code has no run-time choice of registers and every update is in place.
+template <typename T, int R>
+__device__ __forceinline__ void run_chunk_paired(typename Amp<T>::V *__restrict__ st,
+                                                 cptr<DevSection> S, cptr<DevPhase> phases,
+                                                 cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
+                                                 uint64_t chunk, typename Amp<T>::V *lds) {
+    using V = typename Amp<T>::V;
+    const int TB = (int)S->c - R;
+    const unsigned tid = threadIdx.x;
+    const uint64_t base = chunk_base(S, chunk);
+    const cptr<DevPhase> ph = phases + S->phase_begin;
+    const int nph = (int)(S->phase_end - S->phase_begin);
+    V a[1 << R];
+    chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
+    for (int p = 0; p < nph; ++p) {
+        const cptr<DevPhase> P = ph + p;
+        const uint32_t o = P->op_begin;
+        dense_apply<V, R, 0, 1>(a, mats + ops[o].arg);
+        dense_apply<V, R, 2, 3>(a, mats + ops[o + 1].arg);
+        if (p + 1 < nph) chunk_transpose<V, R, true>(a, lds, P->wr, ph[p + 1].rd, tid, TB, true);
+    }
+    chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
+}
+
 // sum over the thread's registers of |a|^2 in FP64
 template <typename V, int R> __device__ __forceinline__ double reg_norm2(const V (&a)[1 << R]) {
     double s = 0.0;

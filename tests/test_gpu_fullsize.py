@@ -253,3 +253,55 @@ def test_qv34_c64_blocked_vs_pergate_and_mirror(torch):
     del a
     assert 1.0 - abs(got[ys == 0][0]) ** 2 < 1e-4
     assert np.max(np.abs(got[ys != 0])) < 1e-4
+
+
+@pytest.mark.parametrize("n,dt,sizes", [(33, B.QSV_C128, [11, 11, 11]),
+                                        (34, B.QSV_C64, [12, 11, 11])])
+def test_grouped_qv_paired_beam_vs_oracle(torch, n, dt, sizes):
+    """The same product-structured check in the paired-phase kernel with the
+    beam-search planner (the options the benchmark's autotuner selects)."""
+    es = 16 if dt == B.QSV_C128 else 8
+    need_bytes(torch, es << n)
+    gates, groups = W.grouped_quantum_volume(n, sizes, n, 2)
+    ctx = B.Context(dt)
+    plan = B.Plan(n, gates, dt, section_kernel=B.QSV_KERNEL_PAIRED, planner=B.QSV_PLANNER_BEAM)
+    st = torch.empty(1 << n, dtype=tdtype(torch, dt), device="cuda")
+    ctx.init_basis(st, n, 0)
+    ctx.apply(plan, st)
+    ys = sample_indices(n, 9)
+    got = gather(torch, st, ys)
+    nrm = ctx.norm(st, n).item()
+    del st
+    want = grouped.product_amplitudes(grouped.group_states(gates, groups), groups, ys)
+    rel = 1e-10 if dt == B.QSV_C128 else 1e-4
+    assert np.max(np.abs(got - want)) <= rel * np.max(np.abs(want))
+    assert abs(nrm - 1.0) < (1e-12 if dt == B.QSV_C128 else 1e-5)
+
+
+def test_qv33_paired_beam_mirror_and_vs_registers(torch):
+    """QV33 complex128 in the paired kernel with the beam planner: its mirror
+    returns |0...0>, and the circuit itself agrees with the register-phase kernel
+    (FP64 device overlap)."""
+    n = 33
+    need_bytes(torch, 2 * (16 << n))
+    gates = W.quantum_volume(n, n, 0)
+    ctx = B.Context(B.QSV_C128)
+    opts = dict(section_kernel=B.QSV_KERNEL_PAIRED, planner=B.QSV_PLANNER_BEAM)
+    a = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    ctx.init_basis(a, n, 0)
+    ctx.apply(B.Plan(n, gates, B.QSV_C128, **opts), a)
+    ctx.init_basis(b, n, 0)
+    ctx.apply(B.Plan(n, gates, B.QSV_C128), b)
+    f, na, nb = fidelity_dev(ctx, a, b, n)
+    del b
+    gc.collect()
+    torch.cuda.empty_cache()
+    assert 1.0 - f < 1e-12 and abs(na - 1.0) < 1e-12
+    ctx.init_basis(a, n, 0)
+    ctx.apply(B.Plan(n, W.mirror(gates), B.QSV_C128, **opts), a)
+    ys = sample_indices(n, 10)
+    got = gather(torch, a, ys)
+    del a
+    assert abs(1.0 - abs(got[ys == 0][0]) ** 2) < 1e-12
+    assert np.max(np.abs(got[ys != 0])) < 1e-7

@@ -371,3 +371,100 @@ def test_beam_and_exact_planner_plans(torch, ctxs, dt):
     got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, planner=B.QSV_PLANNER_EXACT,
                         chunk_bits=5, register_bits=3, pinned_low_bits=1)
     assert_close(got, oracle.apply_circuit(n, gates, psi0), dt, "exact")
+
+
+LDS_CASES = [
+    # n, chunk_bits, fusion, seed
+    (3, 3, 0, 0),
+    (6, 4, 2, 1),      # 16-amplitude chunk: fewer amplitudes than threads
+    (9, 7, 2, 2),
+    (12, 10, 3, 3),
+    (15, 12, 4, 4),
+    (17, 13, 2, 5),
+    (19, 11, 3, 6),
+]
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("n,c,f,seed", LDS_CASES)
+def test_lds_kernel_random_circuits(torch, ctxs, dt, n, c, f, seed):
+    """The LDS-resident section kernel on random circuits of every gate kind
+    (SWAP relabelling, diagonal gates on local and non-local qubits, CX with local
+    and non-local controls, dense gates up to 4 qubits after fusion)."""
+    gates = W.random_circuit(n, 6 * n + 10, 50 + seed, max_unitary_qubits=min(3, n))
+    psi0 = random_state(n, seed)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=c, fusion_max_qubits=f,
+                        section_kernel=B.QSV_KERNEL_LDS, pinned_low_bits=min(3, c - 2))
+    assert plan.stats()["register_bits"] == min(c, n)
+    assert_close(got, want, dt, "lds")
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_lds_kernel_qv_and_wide(torch, ctxs, dt):
+    n = 20
+    gates = W.quantum_volume(n, n, 9)
+    psi0 = random_state(n, 9)
+    for f in (2, 3, 4):
+        got, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, section_kernel=B.QSV_KERNEL_LDS,
+                         fusion_max_qubits=f)
+        assert_close(got, oracle.apply_circuit(n, gates, psi0), dt, "lds qv f=%d" % f)
+    rng = np.random.default_rng(4)
+    wide = [W.Gate("unitary", tuple(int(v) for v in rng.choice(14, size=4, replace=False)), (),
+                   W.haar_unitary(rng, 16)) for _ in range(5)]
+    psi0 = random_state(14, 4)
+    got, _ = run_gpu(torch, ctxs, 14, wide, dt, psi0=psi0, chunk_bits=10,
+                     section_kernel=B.QSV_KERNEL_LDS)
+    assert_close(got, oracle.apply_circuit(14, wide, psi0), dt, "lds 4-qubit unitaries")
+
+
+PAIRED_CASES = [
+    # n, chunk_bits, seed
+    (6, 4, 0), (9, 6, 1), (12, 8, 2), (16, 12, 3), (18, 13, 4), (20, 11, 5),
+]
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("n,c,seed", PAIRED_CASES)
+def test_paired_sections_qv(torch, ctxs, dt, n, c, seed):
+    """Paired phases (two fused gate pairs at fixed register positions) on
+    Quantum-Volume circuits, several phases per section and one-pair phases."""
+    gates = W.quantum_volume(n, n, 30 + seed)
+    psi0 = random_state(n, seed)
+    want = oracle.apply_circuit(n, gates, psi0)
+    for planner in (B.QSV_PLANNER_DEFAULT, B.QSV_PLANNER_BEAM):
+        got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=c,
+                            section_kernel=B.QSV_KERNEL_PAIRED, planner=planner,
+                            pinned_low_bits=min(3, c - 4))
+        assert plan.stats()["register_bits"] == 4
+        assert_close(got, want, dt, "paired planner %d" % planner)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_paired_mixed_sections(torch, ctxs, dt):
+    """Circuits whose sections mix 2-qubit dense gates with other kinds: the
+    eligible sections run paired phases, the others the general register phases
+    (same plan, both kernels), and the result matches the oracle."""
+    n = 16
+    rng = np.random.default_rng(8)
+    gates = []
+    for layer in range(10):
+        perm = rng.permutation(n)
+        for i in range(n // 2):
+            gates.append(W.Gate("unitary", (int(perm[2 * i]), int(perm[2 * i + 1])), (),
+                                W.haar_su(rng, 4)))
+        if layer % 3 == 2:
+            gates += W.random_circuit(n, 12, 100 + layer, max_unitary_qubits=3)
+    psi0 = random_state(n, 8)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=10,
+                        section_kernel=B.QSV_KERNEL_PAIRED)
+    assert_close(got, oracle.apply_circuit(n, gates, psi0), dt, "paired mixed")
+    # the same plan through the batch kernel (general phases execute paired tables)
+    if dt == B.QSV_C64:
+        plans = [B.Plan(n, gates, dt, chunk_bits=11, section_kernel=B.QSV_KERNEL_PAIRED)]
+        st = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+        ctxs[dt].batch_run(plans, [0], st)
+        torch.cuda.synchronize()
+        want = oracle.apply_circuit(n, gates)
+        got = st.cpu().numpy().astype(np.complex128)
+        assert 1.0 - oracle.fidelity(got, want) < 1e-5

@@ -401,3 +401,21 @@ def test_host_stream_schedule():
     with pytest.raises(B.QsvError) as e:
         p.stream_bits(n - c + 1)
     assert e.value.status == -4
+
+
+def test_lds_kernel_plan_validation():
+    n = 10
+    p = B.Plan(n, W.quantum_volume(n, n, 0), B.QSV_C128, chunk_bits=8,
+               section_kernel=B.QSV_KERNEL_LDS)
+    st = p.stats()
+    assert st["register_bits"] == 8 and st["n_phases"] == st["n_sections"]
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(n, W.hardware_efficient_ansatz(n, 1), B.QSV_C128, section_kernel=B.QSV_KERNEL_LDS)
+    assert e.value.status == -4
+    rng = np.random.default_rng(0)
+    g5 = [W.Gate("unitary", (0, 1, 2, 3, 4), (), W.haar_unitary(rng, 32))]
+    with pytest.raises(B.QsvError) as e:
+        B.Plan(n, g5, B.QSV_C128, section_kernel=B.QSV_KERNEL_LDS)
+    assert e.value.status == -4
+    with pytest.raises(B.QsvError):
+        B.Plan(n, W.ghz(n), B.QSV_C128, section_kernel=7)
