@@ -256,8 +256,11 @@ k_adjoint_section(typename Amp<T>::V *__restrict__ psi_g, typename Amp<T>::V *__
             op_inverse<T, R, KMAX>(lam, op, mats, ptab, pbase, base);
         }
         if (p > 0) {
-            chunk_transpose<V, R>(psi, lds, P->rd, ph[p - 1].wr, tid, TB, true);
-            chunk_transpose<V, R>(lam, lds, P->rd, ph[p - 1].wr, tid, TB, true);
+            // the reverse of the transposition after phase p - 1: write in its
+            // read layout, read in its write layout
+            const cptr<DevPhase> Q = ph + (p - 1);
+            chunk_transpose<V, R>(psi, lds, P->rd, Q->wr, Q->xr, Q->xw, tid, TB, true);
+            chunk_transpose<V, R>(lam, lds, P->rd, Q->wr, Q->xr, Q->xw, tid, TB, true);
         }
     }
     if (whole_waves && S->n_params_used > 0) {

@@ -728,6 +728,93 @@ std::vector<POp> fuse(const std::vector<POp> &in, int f) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// LDS swizzle of each transposition
+//
+// A transposition writes every amplitude component to LDS element index
+// x = sum of 2^slot over its set data positions and reads it back under the
+// next phase's map.  The element actually used is x ^ M(x), M linear with
+// M(2^s) = swz[s] holding only bits below min(s, T): a unitriangular map, so a
+// permutation of the buffer.  Lanes of one wave are thread bits 0..5 (data
+// positions R..R+5); the LDS serves a group of consecutive lanes per cycle, and
+// the group is conflict-free when the low bits of its addresses (the bank) are
+// distinct, i.e. when the low-T projections of the lanes' address vectors
+// 2^s ^ swz[s] are linearly independent.  The masks are searched so that this
+// holds for both the write map and the read map, for 128-byte and 256-byte
+// bank rows (T = log2 of the row's elements), with a fixed-seed search.  The
+// phase stores the per-position vectors (xw, xr), so the kernel indexes no
+// table at run time.
+
+static int gf2_rank(uint32_t *v, int m) {
+    int rank = 0;
+    for (int bit = 31; bit >= 0 && rank < m; --bit) {
+        int piv = -1;
+        for (int i = rank; i < m; ++i)
+            if ((v[i] >> bit) & 1u) { piv = i; break; }
+        if (piv < 0) continue;
+        std::swap(v[rank], v[piv]);
+        for (int i = 0; i < m; ++i)
+            if (i != rank && ((v[i] >> bit) & 1u)) v[i] ^= v[rank];
+        ++rank;
+    }
+    return rank;
+}
+
+static void assign_swizzles(Plan &P, const DevSection &ds, int R) {
+    const int C = (int)ds.c;
+    const int EB = P.dtype == QSV_C128 ? 8 : 4;        // component bytes
+    const int TB = C - R;                               // thread bits
+    const int L = std::min(6, TB);                      // lane bits of one wave
+    const int T1 = std::min(C, EB == 8 ? 4 : 5);        // 128-byte bank row
+    const int T2 = std::min(C, T1 + 1);                 // 256-byte bank row
+    auto score = [&](const uint8_t *map, const uint8_t *col) {
+        int sc = 0;
+        for (int T : {T1, T2}) {
+            const int m = std::min(T, L);
+            uint32_t v[8];
+            for (int b = 0; b < m; ++b) {
+                const int s = map[R + b];
+                v[b] = ((1u << s) ^ col[s]) & ((1u << T) - 1u);
+            }
+            sc += gf2_rank(v, m);
+        }
+        return sc;
+    };
+    int best_possible = 0;
+    for (int T : {T1, T2}) best_possible += 2 * std::min(T, L);
+    uint64_t rng = 0x9E3779B97F4A7C15ull;
+    auto next = [&]() {
+        rng ^= rng << 13;
+        rng ^= rng >> 7;
+        rng ^= rng << 17;
+        return rng;
+    };
+    for (uint32_t p = ds.phase_begin; p + 1 < ds.phase_end; ++p) {
+        DevPhase &a = P.dphase[p];
+        const uint8_t *wr = a.wr, *rd = P.dphase[p + 1].rd;
+        uint8_t best[16] = {0}, col[16] = {0};
+        int best_sc = score(wr, best) + score(rd, best);
+        // only the lane slots of either map need a mask
+        bool lane_slot[16] = {false};
+        for (int b = 0; b < L; ++b) lane_slot[wr[R + b]] = lane_slot[rd[R + b]] = true;
+        for (int it = 0; it < 4096 && best_sc < best_possible; ++it) {
+            for (int s = 0; s < C; ++s) {
+                const int lim = std::min(s, T2);
+                col[s] = (lane_slot[s] && lim > 0) ? (uint8_t)(next() & ((1u << lim) - 1u)) : 0;
+            }
+            const int sc = score(wr, col) + score(rd, col);
+            if (sc > best_sc) {
+                best_sc = sc;
+                std::memcpy(best, col, sizeof(best));
+            }
+        }
+        for (int q = 0; q < C; ++q) {
+            a.xw[q] = (uint16_t)((1u << wr[q]) ^ best[wr[q]]);
+            a.xr[q] = (uint16_t)((1u << rd[q]) ^ best[rd[q]]);
+        }
+    }
+}
+
 static void lower_section(Plan &P, int si) {
     HostSection &S = P.sections[si];
     const int C = (int)S.phys_local.size();
@@ -997,6 +1084,7 @@ static void lower_section(Plan &P, int si) {
         }
         if (moves && ds.phase_end - ds.phase_begin == 1) ds.flags |= SEC_SYNC_SCATTER;
     }
+    assign_swizzles(P, ds, R);
     P.dsec.push_back(ds);
 }
 
@@ -1132,6 +1220,7 @@ static void lower_section_paired(Plan &P, int si) {
         ds.gather_phys[q] = ds.slot_phys[f.rd[q]];
         ds.scatter_phys[q] = ds.slot_phys[l.wr[q]];
     }
+    assign_swizzles(P, ds, 4);
     P.dsec.push_back(ds);
 }
 

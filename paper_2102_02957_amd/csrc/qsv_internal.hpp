@@ -58,13 +58,19 @@ struct DevOp {               // 16 bytes
 };
 static_assert(sizeof(DevOp) == 16, "DevOp layout");
 
-struct DevPhase {            // 48 bytes
+struct DevPhase {            // 128 bytes
     uint8_t rd[16];          // data position -> chunk slot at the phase start
     uint8_t wr[16];          // data position -> chunk slot at the phase end
+    // The LDS transposition into the next phase, as element-index masks per data
+    // position: element index = XOR of the masks of the set position bits.  xw
+    // from this phase's wr map, xr from the next phase's rd map, both with the
+    // transposition's swizzle applied (its bank-conflict-free layout).
+    uint16_t xw[16];
+    uint16_t xr[16];
     uint32_t op_begin, op_end;
-    uint32_t pad[2];
+    uint32_t pad[6];
 };
-static_assert(sizeof(DevPhase) == 48, "DevPhase layout");
+static_assert(sizeof(DevPhase) == 128, "DevPhase layout");
 
 struct DevSection {          // 128 bytes
     uint8_t slot_phys[16];   // chunk slot -> physical bit (ascending)

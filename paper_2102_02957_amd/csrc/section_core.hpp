@@ -64,6 +64,21 @@ __device__ __forceinline__ Bytes16 ld16(cptr<uint8_t> p) {  // p 4-byte aligned
     return b;
 }
 
+// 16-bit tables, likewise a dword at a time.
+struct Half16 {
+    uint32_t w[8];
+    __device__ __forceinline__ uint32_t operator[](int i) const {
+        return (w[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+    }
+};
+__device__ __forceinline__ Half16 ld16h(cptr<uint16_t> p) {  // p 4-byte aligned
+    const cptr<uint32_t> q = (cptr<uint32_t>)p;
+    Half16 h;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) h.w[i] = q[i];
+    return h;
+}
+
 // One in-section op, decoded from its four dwords (scalar registers).
 struct OpH {
     uint32_t type, k, a[5], rot;
@@ -384,33 +399,59 @@ __device__ __forceinline__ void lds_barrier() {
 // instead of two: for HBM-resident states the extra one hides more latency
 // than the barriers cost.  Threads with active == false take part in the
 // barriers only.
+//
+// With SPLIT the layout is the plan's: xw_tab / xr_tab give per data position
+// the element-index vector of the write and the read map, the swizzle chosen
+// per transposition already applied (lanes served together hit distinct
+// banks for both maps).  Otherwise (from_tab / to_tab) the fixed lds_swizzle.
+// Both layouts are GF(2)-linear, so every address is the thread's part XOR a
+// uniform register part.
 template <typename V, int R, bool SPLIT = true>
 __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uint8_t> from_tab,
-                                                cptr<uint8_t> to_tab, unsigned tid, int TB,
+                                                cptr<uint8_t> to_tab, cptr<uint16_t> xw_tab,
+                                                cptr<uint16_t> xr_tab, unsigned tid, int TB,
                                                 bool active) {
     using E = decltype(V{}.x);
     typedef E __attribute__((ext_vector_type(2))) E2;
     using L = typename std::conditional<SPLIT, E, E2>::type;  // LDS element
     constexpr int EB = sizeof(L);
     static_assert(EB == 4 || EB == 8 || EB == 16, "float or double components");
-    const Bytes16 from = ld16(from_tab), to = ld16(to_tab);
-    uint32_t tw = 0, tr = 0;
-    static_for<9>([&](auto B) __attribute__((always_inline)) {
-        if (B.value < TB) {
-            tw |= ((tid >> B.value) & 1u) << from[R + B.value];
-            tr |= ((tid >> B.value) & 1u) << to[R + B.value];
-        }
-    });
     // byte offsets: thread part (per lane) ^ register part (uniform, one scalar
     // value per register bit, combined per element)
     const uint32_t lbase = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char *)lds;
-    const uint32_t tws = lds_swizzle<EB>(tw) * EB;
-    const uint32_t trs = lds_swizzle<EB>(tr) * EB;
+    uint32_t tws = 0, trs = 0;
     uint32_t sw[R], sr[R];
-    static_for<R>([&](auto B) __attribute__((always_inline)) {
-        sw[B.value] = lds_swizzle<EB>(1u << from[B.value]) * EB;
-        sr[B.value] = lds_swizzle<EB>(1u << to[B.value]) * EB;
-    });
+    if constexpr (SPLIT) {
+        const Half16 xw = ld16h(xw_tab), xr = ld16h(xr_tab);
+        static_for<9>([&](auto B) __attribute__((always_inline)) {
+            if (B.value < TB) {
+                const bool on = (tid >> B.value) & 1u;
+                tws ^= on ? xw[R + B.value] : 0u;
+                trs ^= on ? xr[R + B.value] : 0u;
+            }
+        });
+        tws *= EB;
+        trs *= EB;
+        static_for<R>([&](auto B) __attribute__((always_inline)) {
+            sw[B.value] = xw[B.value] * EB;
+            sr[B.value] = xr[B.value] * EB;
+        });
+    } else {
+        const Bytes16 from = ld16(from_tab), to = ld16(to_tab);
+        uint32_t tw = 0, tr = 0;
+        static_for<9>([&](auto B) __attribute__((always_inline)) {
+            if (B.value < TB) {
+                tw |= ((tid >> B.value) & 1u) << from[R + B.value];
+                tr |= ((tid >> B.value) & 1u) << to[R + B.value];
+            }
+        });
+        tws = lds_swizzle<EB>(tw) * EB;
+        trs = lds_swizzle<EB>(tr) * EB;
+        static_for<R>([&](auto B) __attribute__((always_inline)) {
+            sw[B.value] = lds_swizzle<EB>(1u << from[B.value]) * EB;
+            sr[B.value] = lds_swizzle<EB>(1u << to[B.value]) * EB;
+        });
+    }
     static_for<SPLIT ? 2 : 1>([&](auto H) __attribute__((always_inline)) {
         lds_barrier();  // the previous pass's reads are done before this pass writes
         if (active) {
@@ -571,7 +612,7 @@ __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cp
         const cptr<DevPhase> P = ph + p;
         chunk_ops<T, R, KMAX, DENSE_ONLY>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
         if (p + 1 < nph)
-            chunk_transpose<V, R, SPLIT>(a, lds, P->wr, ph[p + 1].rd, tid, TB, active);
+            chunk_transpose<V, R, SPLIT>(a, lds, P->wr, ph[p + 1].rd, P->xw, P->xr, tid, TB, active);
     }
 }
 
@@ -616,7 +657,8 @@ __device__ __forceinline__ void run_chunk_paired(typename Amp<T>::V *__restrict_
         const uint32_t o = P->op_begin;
         dense_apply<V, R, 0, 1>(a, mats + ops[o].arg);
         dense_apply<V, R, 2, 3>(a, mats + ops[o + 1].arg);
-        if (p + 1 < nph) chunk_transpose<V, R, true>(a, lds, P->wr, ph[p + 1].rd, tid, TB, true);
+        if (p + 1 < nph)
+            chunk_transpose<V, R, true>(a, lds, P->wr, ph[p + 1].rd, P->xw, P->xr, tid, TB, true);
     }
     chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
 }
