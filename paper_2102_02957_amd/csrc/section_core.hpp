@@ -422,16 +422,29 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
     uint32_t tws = 0, trs = 0;
     uint32_t sw[R], sr[R];
     if constexpr (SPLIT) {
+        // Entries past the chunk's positions are zero and every thread of a
+        // SPLIT caller has tid < 2^TB, so no bit needs a TB test.  Bits 0..5 are
+        // the lane's (vector ops); bits 6..8 are the wave's (scalar ops).
         const Half16 xw = ld16h(xw_tab), xr = ld16h(xr_tab);
-        static_for<9>([&](auto B) __attribute__((always_inline)) {
-            if (B.value < TB) {
-                const bool on = (tid >> B.value) & 1u;
-                tws ^= on ? xw[R + B.value] : 0u;
-                trs ^= on ? xr[R + B.value] : 0u;
+        static_for<6>([&](auto B) __attribute__((always_inline)) {
+            if constexpr (R + B.value < 16) {
+                const uint32_t on = (uint32_t)((int32_t)(tid << (31 - B.value)) >> 31);  // 0 or ~0
+                tws ^= on & xw[R + B.value];
+                trs ^= on & xr[R + B.value];
             }
         });
-        tws *= EB;
-        trs *= EB;
+        const uint32_t wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+        uint32_t uw = 0, ur = 0;
+        static_for<3>([&](auto B) __attribute__((always_inline)) {
+            if constexpr (R + 6 + B.value < 16) {
+                if ((wid >> B.value) & 1u) {
+                    uw ^= xw[R + 6 + B.value];
+                    ur ^= xr[R + 6 + B.value];
+                }
+            }
+        });
+        tws = (tws ^ uw) * EB;
+        trs = (trs ^ ur) * EB;
         static_for<R>([&](auto B) __attribute__((always_inline)) {
             sw[B.value] = xw[B.value] * EB;
             sr[B.value] = xr[B.value] * EB;
