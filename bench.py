@@ -51,9 +51,10 @@ def parse():
     ap.add_argument("--register-bits", type=int, default=None)
     ap.add_argument("--io-phases", type=int, default=None)
     ap.add_argument("--section-kernel", type=int, default=None,
-                    help="0: register-phase kernel, 1: LDS-resident chunk")
+                    help="0: register-phase kernel, 1: LDS-resident chunk, 2: paired register "
+                         "phases, 3: LDS-resident chunk with fused 4-5 qubit blocks on MFMA")
     ap.add_argument("--planner", type=int, default=None,
-                    help="0 default, 1 greedy, 2 beam search")
+                    help="0 default, 1 greedy, 2 beam search, 3 exact (small circuits)")
     ap.add_argument("--autotune", choices=["live", "cache", "off"], default="live",
                     help="live: tune on this workload now (the default); cache: reuse a stored "
                          "result for the same (arch, dtype, n, circuit) if there is one; off: "

@@ -146,10 +146,16 @@ typedef struct {
                                     qubits runs phases of two fused gate pairs at fixed register
                                     positions (the amplitudes are updated in place, no run-time
                                     choice of registers); other sections use the register
-                                    phases; the plan uses 4 register bits */
+                                    phases; the plan uses 4 register bits; QSV_KERNEL_MFMA:
+                                    as QSV_KERNEL_LDS, with in-section gates fused into blocks
+                                    of up to fusion_max_qubits (4 or 5) qubits (commuting gates
+                                    gathered across the section, not only consecutive ones)
+                                    and every dense op of 4 or 5 qubits applied as a complex
+                                    matrix product on the matrix cores (chunk_bits >= 9; gates
+                                    of up to 5 qubits) */
 } qsv_options;
 
-enum { QSV_KERNEL_REGISTERS = 0, QSV_KERNEL_LDS = 1, QSV_KERNEL_PAIRED = 2 };
+enum { QSV_KERNEL_REGISTERS = 0, QSV_KERNEL_LDS = 1, QSV_KERNEL_PAIRED = 2, QSV_KERNEL_MFMA = 3 };
 enum { QSV_PLANNER_DEFAULT = 0, QSV_PLANNER_GREEDY = 1, QSV_PLANNER_BEAM = 2,
        QSV_PLANNER_EXACT = 3 };
 

@@ -19,7 +19,7 @@ QSV_SWAP_REMAP, QSV_SWAP_MATERIALIZE = 0, 1
 QSV_MODE_BLOCKED, QSV_MODE_PER_GATE = 0, 1
 QSV_OP_BEGIN, QSV_OP_END, QSV_OP_CHUNK_SWAP, QSV_OP_GATE = 1, 2, 3, 4
 QSV_PLANNER_DEFAULT, QSV_PLANNER_GREEDY, QSV_PLANNER_BEAM, QSV_PLANNER_EXACT = 0, 1, 2, 3
-QSV_KERNEL_REGISTERS, QSV_KERNEL_LDS, QSV_KERNEL_PAIRED = 0, 1, 2
+QSV_KERNEL_REGISTERS, QSV_KERNEL_LDS, QSV_KERNEL_PAIRED, QSV_KERNEL_MFMA = 0, 1, 2, 3
 
 KINDS = {k: i + 1 for i, k in enumerate(
     ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "rx", "ry", "rz", "p", "u3",
@@ -568,6 +568,12 @@ def state_candidates(dtype, n):
             out.append(dict(chunk_bits=c, register_bits=4, pinned_low_bits=min(3, c - 4),
                             fusion_max_qubits=2, io_phases=0, planner=pl,
                             section_kernel=QSV_KERNEL_PAIRED))
+    # fused 4-qubit blocks on the matrix cores (LDS-resident chunk)
+    c = min(base.chunk_bits, n)
+    if c >= 9:
+        out.append(dict(chunk_bits=c, pinned_low_bits=min(base.pinned_low_bits, c - 5),
+                        fusion_max_qubits=4, io_phases=0, planner=QSV_PLANNER_BEAM,
+                        section_kernel=QSV_KERNEL_MFMA))
     return out
 
 

@@ -203,7 +203,7 @@ qsv_status batch_prepare(qsv_dtype dt, int count, const Plan *const *plans,
             return QSV_E_UNSUPPORTED;
         }
         if (P.n_params > 0 || P.opt.swap_mode != QSV_SWAP_REMAP ||
-            P.opt.section_kernel == QSV_KERNEL_LDS) {
+            lds_resident(P.opt)) {
             // paired tables are ordinary register phases (dense ops at fixed positions)
             err = "batch plans must be remap-mode register-phase plans without parameters";
             return QSV_E_UNSUPPORTED;

@@ -41,10 +41,11 @@ hipError_t launch_section(qsv_dtype dt, int r, int kmax, bool dense_only, void *
 // launch_section (0 for a single phase).
 hipError_t launch_section_paired(qsv_dtype dt, void *state, int n, int batch, DevPlanView pv,
                                  int sec, int c, size_t lds_bytes, hipStream_t s);
-// One section with the chunk resident in LDS (plans with section_kernel = QSV_KERNEL_LDS:
-// one phase per section, op positions = LDS index bits).
-hipError_t launch_section_lds(qsv_dtype dt, int kmax, void *state, int n, int batch, DevPlanView pv,
-                              int sec, int c, hipStream_t s);
+// One section with the chunk resident in LDS (plans with section_kernel = QSV_KERNEL_LDS or
+// QSV_KERNEL_MFMA: one phase per section, op positions = LDS index bits; mfma: dense ops
+// of 4 and 5 qubits on the matrix cores, chunk_bits >= 9).
+hipError_t launch_section_lds(qsv_dtype dt, int kmax, bool mfma, void *state, int n, int batch,
+                              DevPlanView pv, int sec, int c, hipStream_t s);
 // ptab[b][2 i], ptab[b][2 i + 1] for every parameterised op i (see OP_PROT / OP_PDIAG)
 hipError_t launch_param_table(qsv_dtype dt, const double *params, int n_params,
                               const PSlot *slots, int nslots, int batch, void *ptab, hipStream_t s);

@@ -726,6 +726,74 @@ std::vector<POp> fuse(const std::vector<POp> &in, int f) {
     return out;
 }
 
+// positions an op reads or writes (sources outside the chunk excluded)
+uint32_t touched(const POp &o) {
+    if (o.fusable) return o.regmask;
+    uint32_t m = 0;
+    for (int j = 0; j < o.op.k && j < 5; ++j)
+        if (o.op.a[j] < SRC_GLOBAL) m |= 1u << o.op.a[j];
+    if (o.op.type == OP_CX || o.op.type == OP_XREG || o.op.type == OP_PROT) m |= 1u << o.op.a[0];
+    if (o.op.type == OP_CX && o.op.a[1] < SRC_GLOBAL) m |= 1u << o.op.a[1];
+    if (o.op.type == OP_PDIAG && o.op.a[0] < SRC_GLOBAL) m |= 1u << o.op.a[0];
+    return m;
+}
+
+// Block fusion (for the matrix-core path, where a fused op's cost grows with
+// its width, not with the gates in it): starting from the first unplaced op,
+// take every later dense-able op whose positions keep the block within f
+// qubits and that commutes past all ops left behind so far (disjoint
+// positions), multiply them in circuit order, and place the block where its
+// first op was.  Ops left behind keep their order.
+std::vector<POp> fuse_blocks(const std::vector<POp> &in, int f) {
+    if (f < 2) return in;
+    std::vector<POp> out;
+    std::vector<char> used(in.size(), 0);
+    for (size_t i = 0; i < in.size(); ++i) {
+        if (used[i]) continue;
+        used[i] = 1;
+        if (!in[i].fusable) {
+            out.push_back(in[i]);
+            continue;
+        }
+        uint32_t mask = in[i].regmask, blocked = 0;
+        std::vector<size_t> members = {i};
+        for (size_t j = i + 1; j < in.size(); ++j) {
+            if (used[j]) continue;
+            const uint32_t tj = touched(in[j]);
+            if (in[j].fusable && !(tj & blocked) && popc(mask | tj) <= f) {
+                mask |= tj;
+                members.push_back(j);
+                used[j] = 1;
+            } else {
+                blocked |= tj;
+            }
+            if ((mask & ~blocked) == 0) break;  // nothing more can join
+        }
+        if (members.size() == 1) {
+            out.push_back(in[i]);
+            continue;
+        }
+        std::vector<int> pos;
+        for (int p = 0; p < 32; ++p)
+            if ((mask >> p) & 1) pos.push_back(p);
+        size_t d = size_t(1) << pos.size();
+        std::vector<cd> M(d * d, cd(0, 0));
+        for (size_t t = 0; t < d; ++t) M[t * d + t] = 1.0;
+        for (size_t t : members) M = matmul(embed(in[t], pos), M, d);
+        POp F;
+        std::memset(&F.op, 0, sizeof(F.op));
+        F.op.type = OP_DENSE;
+        F.op.k = (uint8_t)pos.size();
+        for (size_t t = 0; t < pos.size(); ++t) F.op.a[t] = (uint8_t)pos[t];
+        F.op.slot = -1;
+        F.m = std::move(M);
+        F.fusable = true;
+        F.regmask = mask;
+        out.push_back(std::move(F));
+    }
+    return out;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1015,7 +1083,8 @@ static void lower_section(Plan &P, int si) {
             pops.push_back(std::move(o));
         }
         int f = std::min(P.fusion_eff, R);
-        std::vector<POp> fused = fuse(pops, f);
+        std::vector<POp> fused = P.opt.section_kernel == QSV_KERNEL_MFMA ? fuse_blocks(pops, f)
+                                                                         : fuse(pops, f);
         for (POp &o : fused) {
             if (o.op.type == OP_DENSE || o.op.type == OP_DIAG) {
                 o.op.arg = (int32_t)P.dmats.size();
@@ -1308,8 +1377,8 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         return QSV_E_INVALID;
     }
     if (o.section_kernel != QSV_KERNEL_REGISTERS && o.section_kernel != QSV_KERNEL_LDS &&
-        o.section_kernel != QSV_KERNEL_PAIRED) {
-        err = "section_kernel must be QSV_KERNEL_REGISTERS, _LDS or _PAIRED";
+        o.section_kernel != QSV_KERNEL_PAIRED && o.section_kernel != QSV_KERNEL_MFMA) {
+        err = "section_kernel must be QSV_KERNEL_REGISTERS, _LDS, _PAIRED or _MFMA";
         return QSV_E_INVALID;
     }
     if (o.planner < QSV_PLANNER_DEFAULT || o.planner > QSV_PLANNER_EXACT) {
@@ -1355,14 +1424,21 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         err = "a gate acts on more qubits than the chunk holds";
         return QSV_E_INVALID;
     }
-    if (o.section_kernel == QSV_KERNEL_LDS) {
+    if (lds_resident(o)) {
         // the whole chunk is one register phase: op positions are LDS index bits
+        const bool mfma = o.section_kernel == QSV_KERNEL_MFMA;
         if (P.n_params > 0) {
             err = "the LDS-resident section kernel takes no bound parameters";
             return QSV_E_UNSUPPORTED;
         }
-        if (maxk > 4) {
-            err = "the LDS-resident section kernel applies dense gates of at most 4 qubits";
+        if (maxk > (mfma ? 5 : 4)) {
+            err = mfma ? "the MFMA section kernel applies dense gates of at most 5 qubits"
+                       : "the LDS-resident section kernel applies dense gates of at most 4 qubits";
+            return QSV_E_UNSUPPORTED;
+        }
+        if (mfma && P.c < 9) {
+            // a 5-qubit op needs at least one tile of 16 amplitude groups
+            err = "the MFMA section kernel needs chunk_bits >= 9";
             return QSV_E_UNSUPPORTED;
         }
         if (n - P.c + std::min(P.c, 9) > 31) {
@@ -1379,7 +1455,7 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
         }
         P.r = 4;
     }
-    if (o.section_kernel != QSV_KERNEL_LDS && P.c - P.r > (P.r <= 4 ? 9 : 8)) {
+    if (!lds_resident(o) && P.c - P.r > (P.r <= 4 ? 9 : 8)) {
         err = "chunk_bits - register_bits must be <= 9 for register_bits <= 4 and <= 8 for "
               "register_bits = 5 (512 / 256 threads per workgroup)";
         return QSV_E_INVALID;
@@ -1398,9 +1474,10 @@ qsv_status build_plan(const qsv_options &opt_in, qsv_dtype dt, int n, const qsv_
     o.chunk_bits = P.c;
     P.opt = o;
     // fused ops run in one thread's registers: at most r qubits, and at most 4
-    // (the widest fused-op kernel instance)
-    P.fusion_eff = o.fusion_max_qubits < 2 ? o.fusion_max_qubits : std::min(o.fusion_max_qubits, std::min(P.r, 4));
-    if (o.section_kernel == QSV_KERNEL_LDS) o.io_phases = 0, P.opt.io_phases = 0;
+    // (the widest fused-op kernel instance); on the matrix cores up to 5
+    const int fmax = o.section_kernel == QSV_KERNEL_MFMA ? 5 : 4;
+    P.fusion_eff = o.fusion_max_qubits < 2 ? o.fusion_max_qubits : std::min(o.fusion_max_qubits, std::min(P.r, fmax));
+    if (lds_resident(o)) o.io_phases = 0, P.opt.io_phases = 0;
 
     if (!block_circuit(P)) {
         err = "the exact planner's search exceeded its state budget (use a smaller circuit or "

@@ -168,6 +168,11 @@ struct Plan {
     uint64_t uid = 0;                       // identity for device-side caching
 };
 
+// plans whose sections keep the chunk in LDS (one phase, op positions = LDS bits)
+inline bool lds_resident(const qsv_options &o) {
+    return o.section_kernel == QSV_KERNEL_LDS || o.section_kernel == QSV_KERNEL_MFMA;
+}
+
 // planner.cpp
 qsv_status build_plan(const qsv_options &opt, qsv_dtype dt, int n, const qsv_gate *g, size_t ng,
                       Plan &out, std::string &err);

@@ -345,8 +345,9 @@ qsv_status run_sections(qsv_ctx *ctx, const Plan &P, const DevPlanView &pv, void
         const size_t lds = section_lds(P, (int)si);
         const bool dense_only = (P.dsec[si].flags & SEC_DENSE_ONLY) != 0;
         qsv_status rc = timed(ctx, 0, s, [&] {
-            if (P.opt.section_kernel == QSV_KERNEL_LDS)
-                return launch_section_lds(P.dtype, P.kmax, state, n, batch, pv, (int)si, P.c, s);
+            if (lds_resident(P.opt))
+                return launch_section_lds(P.dtype, P.kmax, P.opt.section_kernel == QSV_KERNEL_MFMA,
+                                          state, n, batch, pv, (int)si, P.c, s);
             if (P.dsec[si].flags & SEC_PAIRED)
                 return launch_section_paired(P.dtype, state, n, batch, pv, (int)si, P.c, lds, s);
             return launch_section(P.dtype, P.r, P.kmax, dense_only, state, n, batch, pv, (int)si,
@@ -858,8 +859,9 @@ qsv_status qsv_apply_host(qsv_ctx *ctx, const qsv_plan *plan, void *host_state, 
                 (e = hipStreamWaitEvent(h.s_comp, h.ev_in[b], 0)) != hipSuccess)
                 return hip_fail(e, "host streaming: ordering");
             rc = timed(ctx, 0, h.s_comp, [&] {
-                if (P.opt.section_kernel == QSV_KERNEL_LDS)
-                    return launch_section_lds(P.dtype, P.kmax, dev, n - o, 1, sv, (int)si, P.c, h.s_comp);
+                if (lds_resident(P.opt))
+                    return launch_section_lds(P.dtype, P.kmax, P.opt.section_kernel == QSV_KERNEL_MFMA,
+                                              dev, n - o, 1, sv, (int)si, P.c, h.s_comp);
                 if (P.dsec[si].flags & SEC_PAIRED)
                     return launch_section_paired(P.dtype, dev, n - o, 1, sv, (int)si, P.c, lds, h.s_comp);
                 return launch_section(P.dtype, P.r, P.kmax, dense_only, dev, n - o, 1, sv, (int)si,

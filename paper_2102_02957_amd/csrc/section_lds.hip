@@ -9,7 +9,8 @@
 // kernel code depends on which qubits an op touches: each thread takes whole
 // amplitude groups of the op (the pair-wise update of Sec. II-A generalised to
 // 2^k members), reads them from LDS, applies the matrix in registers and
-// writes them back; a barrier separates consecutive ops.
+// writes them back; a barrier separates consecutive ops.  Fused blocks of 4
+// and 5 qubits can instead run on the matrix cores (lds_mfma).
 //
 // LDS index bits are the section's data positions (ascending chunk slots at the
 // start, relabelled by in-section SWAP gates); the LDS address is the index
@@ -80,8 +81,81 @@ __device__ __forceinline__ void lds_dense(V *lds, const uint32_t (&a)[5], cptr<V
     }
 }
 
-template <typename T, int KMAX>
-__global__ void __launch_bounds__(LDS_THREADS)
+// MFMA 16x16x4 blocks (one instruction per element type).  A and B take one
+// element per lane, C and D four: A[i][k] sits in lane i + 16 k and B[k][j] in
+// lane j + 16 k; lane l holds, as its element v, D[4 (l / 16) + v][l % 16] for
+// float and D[l / 16 + 4 v][l % 16] for double (both measured on gfx950).
+typedef double D4 __attribute__((ext_vector_type(4)));
+typedef float F4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ D4 mfma16(double a, double b, D4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ F4 mfma16(float a, float b, F4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Dense 2^K x 2^K op (K = 4, 5: a fused block of gates) on LDS index bits
+// a[0] < ... < a[K-1], as a matrix product on the matrix cores: with the
+// chunk's 2^(c-K) amplitude groups as the columns of X (row = the group
+// member, bits at a[]), Y = U X.  The complex product is four real ones,
+// Yr = Ur Xr - Ui Xi and Yi = Ui Xr + Ur Xi, each built from 16x16x4 blocks:
+// 16 rows of U by 4 members by 16 groups.  A wave owns tiles of 16 groups;
+// it loads all 2^K members of its 16 groups from LDS (B operands: lane j + 16 k
+// takes member 4 s + k of group j at step s), runs the (2^K / 16) x (2^K / 4)
+// x 4 blocks, and writes the results in place (D of row tile t: member
+// 16 t + 4 (l / 16) + v, or 16 t + l / 16 + 4 v for double, of group l % 16).
+// Every group belongs to one wave, so the op needs no barrier
+// inside; the caller's barrier separates it from the next op.  Needs c >= K + 4.
+template <typename V, int K>
+__device__ __forceinline__ void lds_mfma(V *lds, const uint32_t (&a)[5], cptr<V> m, uint32_t c,
+                                         unsigned tid, unsigned nthr) {
+    using E = decltype(V{}.x);
+    typedef E E4 __attribute__((ext_vector_type(4)));
+    constexpr int D = 1 << K, RT = D / 16, KS = D / 4;
+    constexpr bool F64 = sizeof(E) == 8;  // output row order of the double instruction
+    const uint32_t lane = tid & 63u, li = lane & 15u, lk = lane >> 4;
+    const uint32_t wave = tid >> 6, nwaves = nthr >> 6;
+    uint32_t amask = 0;
+    for (int j = 0; j < K; ++j) amask |= 1u << a[j];
+    auto dep = [&](uint32_t r) {  // member index -> LDS index bits
+        uint32_t o = 0;
+        for (int j = 0; j < K; ++j) o |= ((r >> j) & 1u) << a[j];
+        return o;
+    };
+    // lane bits 4-5 give member bits 0-1 of a B element, and bits 2-3 (float) or
+    // 0-1 (double) of a D element
+    const uint32_t in_lane = swz<V>(dep(lk)), out_lane = swz<V>(dep(F64 ? lk : 4u * lk));
+    const uint32_t ntiles = 1u << (c - K - 4);
+    for (uint32_t t = wave; t < ntiles; t += nwaves) {
+        const uint32_t gb = swz<V>(insert_zeros(t * 16u + li, amask));
+        V x[KS];
+        static_for<KS>([&](auto S) __attribute__((always_inline)) {
+            x[S.value] = lds[gb ^ in_lane ^ swz<V>(dep(4u * S.value))];
+        });
+        static_for<RT>([&](auto T) __attribute__((always_inline)) {
+            E4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+            static_for<KS>([&](auto S) __attribute__((always_inline)) {
+                const V u = ldc(m + ((T.value * 16 + li) * D + 4 * S.value + lk));
+                yr = mfma16(u.x, x[S.value].x, yr);
+                yr = mfma16(-u.y, x[S.value].y, yr);
+                yi = mfma16(u.y, x[S.value].x, yi);
+                yi = mfma16(u.x, x[S.value].y, yi);
+            });
+            static_for<4>([&](auto W) __attribute__((always_inline)) {
+                V y;
+                y.x = yr[W.value];
+                y.y = yi[W.value];
+                lds[gb ^ out_lane ^ swz<V>(dep(16u * T.value + (F64 ? 4u * W.value : W.value)))] = y;
+            });
+        });
+    }
+}
+
+// KMAX: widest dense op applied on the vector units.  MFMA: dense ops of 4
+// and 5 qubits go to the matrix cores.  At most 128 registers per lane, so
+// that two 512-thread workgroups (two 64 KiB chunks) share a compute unit.
+template <typename T, int KMAX, bool MFMA>
+__global__ void __launch_bounds__(LDS_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 k_section_lds(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__restrict__ secs_g,
               int sec, const DevPhase *__restrict__ phases_g, const DevOp *__restrict__ ops_g,
               const typename Amp<T>::V *__restrict__ mats_g) {
@@ -126,21 +200,29 @@ k_section_lds(typename Amp<T>::V *__restrict__ state, int n, const DevSection *_
                 case 1: lds_dense<V, 1>(lds, a, mm, c, tid, nthr); break;
                 case 2: lds_dense<V, 2>(lds, a, mm, c, tid, nthr); break;
                 case 3: if constexpr (KMAX >= 3) lds_dense<V, 3>(lds, a, mm, c, tid, nthr); break;
-                case 4: if constexpr (KMAX >= 4) lds_dense<V, 4>(lds, a, mm, c, tid, nthr); break;
+                case 4:
+                    if constexpr (MFMA) lds_mfma<V, 4>(lds, a, mm, c, tid, nthr);
+                    else if constexpr (KMAX >= 4) lds_dense<V, 4>(lds, a, mm, c, tid, nthr);
+                    break;
+                case 5: if constexpr (MFMA) lds_mfma<V, 5>(lds, a, mm, c, tid, nthr); break;
                 default: break;
             }
         } else if (op.type == OP_DIAG) {
             // diagonal over its k bit sources (LDS index bits or the chunk's global bits)
             const cptr<V> tab = mats + op.arg;
+            // (fixed-length loops keep the tables in registers)
             uint32_t gsel = 0, lmask[5];
-            for (uint32_t j = 0; j < op.k; ++j) {
-                const uint32_t s = a[j];
-                lmask[j] = s >= SRC_GLOBAL ? 0u : (1u << s);
-                if (s >= SRC_GLOBAL) gsel |= (uint32_t)((base >> (s - SRC_GLOBAL)) & 1ull) << j;
-            }
+            static_for<5>([&](auto J) __attribute__((always_inline)) {
+                const uint32_t s = a[J.value];
+                const bool on = J.value < (int)op.k;
+                lmask[J.value] = (!on || s >= SRC_GLOBAL) ? 0u : (1u << s);
+                if (on && s >= SRC_GLOBAL) gsel |= (uint32_t)((base >> (s - SRC_GLOBAL)) & 1ull) << J.value;
+            });
             for (uint32_t i = tid; i < N; i += nthr) {
                 uint32_t sel = gsel;
-                for (uint32_t j = 0; j < op.k; ++j) sel |= ((i & lmask[j]) != 0 ? 1u : 0u) << j;
+                static_for<5>([&](auto J) __attribute__((always_inline)) {
+                    sel |= ((i & lmask[J.value]) != 0 ? 1u : 0u) << J.value;
+                });
                 const uint32_t ad = swz<V>(i);
                 lds[ad] = cmul(ldc(tab + sel), lds[ad]);
             }
@@ -181,35 +263,37 @@ k_section_lds(typename Amp<T>::V *__restrict__ state, int n, const DevSection *_
     }
 }
 
-template <typename T, int KMAX>
+template <typename T, int KMAX, bool MFMA>
 hipError_t launch_lds_t(void *state, int n, int batch, DevPlanView pv, int sec, int c, hipStream_t s) {
     using V = typename Amp<T>::V;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_section_lds<T, KMAX>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_section_lds<T, KMAX, MFMA>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const size_t lds = (size_t(1) << c) * sizeof(V);
-    if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    if (lds > 160 * 1024 || (MFMA && c < 9)) return hipErrorInvalidConfiguration;
     const unsigned threads = (unsigned)std::min<uint64_t>(LDS_THREADS, std::max<uint64_t>(64, 1ull << c));
     dim3 grid((unsigned)(1ull << (n - c)), (unsigned)batch);
-    hipLaunchKernelGGL((k_section_lds<T, KMAX>), grid, dim3(threads), lds, s, (V *)state, n, pv.secs,
+    hipLaunchKernelGGL((k_section_lds<T, KMAX, MFMA>), grid, dim3(threads), lds, s, (V *)state, n, pv.secs,
                        sec, pv.phases, pv.ops, (const V *)pv.mats);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_section_lds(qsv_dtype dt, int kmax, void *state, int n, int batch, DevPlanView pv,
-                              int sec, int c, hipStream_t s) {
+hipError_t launch_section_lds(qsv_dtype dt, int kmax, bool mfma, void *state, int n, int batch,
+                              DevPlanView pv, int sec, int c, hipStream_t s) {
     if (dt == QSV_C128) {
-        if (kmax <= 2) return launch_lds_t<double, 2>(state, n, batch, pv, sec, c, s);
-        return launch_lds_t<double, 4>(state, n, batch, pv, sec, c, s);
+        if (mfma) return launch_lds_t<double, 3, true>(state, n, batch, pv, sec, c, s);
+        if (kmax <= 2) return launch_lds_t<double, 2, false>(state, n, batch, pv, sec, c, s);
+        return launch_lds_t<double, 4, false>(state, n, batch, pv, sec, c, s);
     }
-    if (kmax <= 2) return launch_lds_t<float, 2>(state, n, batch, pv, sec, c, s);
-    return launch_lds_t<float, 4>(state, n, batch, pv, sec, c, s);
+    if (mfma) return launch_lds_t<float, 3, true>(state, n, batch, pv, sec, c, s);
+    if (kmax <= 2) return launch_lds_t<float, 2, false>(state, n, batch, pv, sec, c, s);
+    return launch_lds_t<float, 4, false>(state, n, batch, pv, sec, c, s);
 }
 
 }  // namespace qsv

@@ -418,6 +418,56 @@ def test_lds_kernel_qv_and_wide(torch, ctxs, dt):
     assert_close(got, oracle.apply_circuit(14, wide, psi0), dt, "lds 4-qubit unitaries")
 
 
+MFMA_CASES = [
+    # n, chunk_bits, fusion, seed
+    (9, 9, 4, 0),      # one chunk; 5-qubit blocks fill a single tile of 16 groups
+    (12, 9, 5, 1),
+    (14, 10, 4, 2),
+    (16, 12, 5, 3),
+    (18, 13, 5, 4),
+    (20, 11, 4, 5),
+]
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+@pytest.mark.parametrize("n,c,f,seed", MFMA_CASES)
+def test_mfma_fused_blocks(torch, ctxs, dt, n, c, f, seed):
+    """Matrix-core section path: in-section gates fused into blocks of up to f
+    qubits (commuting gates gathered across the section) and applied as complex
+    matrix products with MFMA; random circuits of every gate kind (diagonal and
+    CX with non-local sources stay separate ops) followed by QV layers."""
+    gates = (W.random_circuit(n, 6 * n + 10, 70 + seed, max_unitary_qubits=3)
+             + W.quantum_volume(n, 6, 80 + seed))
+    psi0 = random_state(n, seed)
+    want = oracle.apply_circuit(n, gates, psi0)
+    got, plan = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=c, fusion_max_qubits=f,
+                        section_kernel=B.QSV_KERNEL_MFMA, pinned_low_bits=min(3, c - 5))
+    assert plan.stats()["fusion_max_qubits"] == f
+    assert_close(got, want, dt, "mfma f=%d" % f)
+
+
+@pytest.mark.parametrize("dt", [B.QSV_C128, B.QSV_C64])
+def test_mfma_wide_unitaries_and_qv(torch, ctxs, dt):
+    """Unfused 4- and 5-qubit Haar unitaries on scattered qubits, and a QV
+    circuit at fusion 4 and 5, through the matrix-core path."""
+    rng = np.random.default_rng(12)
+    n = 15
+    wide = [W.Gate("unitary", tuple(int(v) for v in rng.choice(n, size=k, replace=False)), (),
+                   W.haar_unitary(rng, 1 << k)) for k in (4, 5, 5, 4, 5, 3, 5)]
+    psi0 = random_state(n, 12)
+    got, _ = run_gpu(torch, ctxs, n, wide, dt, psi0=psi0, chunk_bits=11, fusion_max_qubits=0,
+                     section_kernel=B.QSV_KERNEL_MFMA)
+    assert_close(got, oracle.apply_circuit(n, wide, psi0), dt, "mfma wide unitaries")
+    n = 20
+    gates = W.quantum_volume(n, n, 13)
+    psi0 = random_state(n, 13)
+    want = oracle.apply_circuit(n, gates, psi0)
+    for f in (4, 5):
+        got, _ = run_gpu(torch, ctxs, n, gates, dt, psi0=psi0, chunk_bits=12 if dt == B.QSV_C128 else 13,
+                         fusion_max_qubits=f, section_kernel=B.QSV_KERNEL_MFMA)
+        assert_close(got, want, dt, "mfma qv f=%d" % f)
+
+
 PAIRED_CASES = [
     # n, chunk_bits, seed
     (6, 4, 0), (9, 6, 1), (12, 8, 2), (16, 12, 3), (18, 13, 4), (20, 11, 5),

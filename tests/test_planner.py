@@ -403,6 +403,35 @@ def test_host_stream_schedule():
     assert e.value.status == -4
 
 
+def test_mfma_plan_validation_and_block_fusion():
+    """Matrix-core plans: gates of up to 5 qubits, fusion up to 5, chunk_bits >= 9,
+    no bound parameters; block fusion gathers commuting gates into fewer ops
+    than fusing consecutive gates only."""
+    n = 12
+    rng = np.random.default_rng(0)
+    g5 = [W.Gate("unitary", (0, 3, 5, 8, 11), (), W.haar_unitary(rng, 32))]
+    p = B.Plan(n, g5, B.QSV_C128, chunk_bits=10, section_kernel=B.QSV_KERNEL_MFMA)
+    assert p.stats()["register_bits"] == 10
+    for bad in (dict(chunk_bits=8), dict(chunk_bits=10, gates=W.hardware_efficient_ansatz(n, 1))):
+        gates = bad.pop("gates", g5)
+        with pytest.raises(B.QsvError) as e:
+            B.Plan(n, gates, B.QSV_C128, section_kernel=B.QSV_KERNEL_MFMA, **bad)
+        assert e.value.status == -4
+    qv = W.quantum_volume(20, 20, 0)
+    st_l = B.Plan(20, qv, B.QSV_C64, chunk_bits=12, section_kernel=B.QSV_KERNEL_LDS,
+                  fusion_max_qubits=5).stats()
+    st_m = B.Plan(20, qv, B.QSV_C64, chunk_bits=12, section_kernel=B.QSV_KERNEL_MFMA,
+                  fusion_max_qubits=5).stats()
+    assert st_l["fusion_max_qubits"] == 4 and st_m["fusion_max_qubits"] == 5
+    st_l4 = B.Plan(20, qv, B.QSV_C64, chunk_bits=12, section_kernel=B.QSV_KERNEL_LDS,
+                   fusion_max_qubits=4).stats()
+    st_m4 = B.Plan(20, qv, B.QSV_C64, chunk_bits=12, section_kernel=B.QSV_KERNEL_MFMA,
+                   fusion_max_qubits=4).stats()
+    assert st_m4["n_sections"] == st_l4["n_sections"]
+    assert st_m4["n_device_ops"] < st_l4["n_device_ops"]
+    assert st_m["n_device_ops"] < st_m4["n_device_ops"]
+
+
 def test_lds_kernel_plan_validation():
     n = 10
     p = B.Plan(n, W.quantum_volume(n, n, 0), B.QSV_C128, chunk_bits=8,
