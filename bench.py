@@ -78,7 +78,8 @@ def log(msg):
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("section_core.hpp", "section_kernels.hpp", "section_kernel.hip", "section_c128.hip",
-              "section_c64.hip", "device.hpp", "qsv_internal.hpp", "planner.cpp"):
+              "section_c64.hip", "section_paired.hip", "section_lds.hip", "device.hpp",
+              "qsv_internal.hpp", "planner.cpp"):
         with open(os.path.join(ROOT, "paper_2102_02957_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -144,7 +145,18 @@ def _cpu_baseline(n_target, gates_target, blocked_bytes, seed):
     }
 
 
-def roofline(st, dt, B, steps, pass_bytes, achieved_gbs, avg_launch_ms, sec_ms, launches, traffic):
+SECTION_KERNELS = {0: "registers", 1: "lds", 2: "paired", 3: "mfma"}
+
+
+def section_kernel_name(kind, dt, B, r):
+    t = "double" if dt == B.QSV_C128 else "float"
+    return {1: "k_section_lds<%s, ...>" % t,
+            2: "k_section_paired<%s>" % t,
+            3: "k_section_lds<%s, 3, true> (MFMA blocks)" % t}.get(kind, "k_section<%s, %d, ...>" % (t, r))
+
+
+def roofline(st, dt, B, steps, pass_bytes, achieved_gbs, avg_launch_ms, sec_ms, launches, traffic,
+             kind=0):
     """The section kernel against both of its rooflines.  Per launch it moves one
     pass (2 * 2^n * es bytes) and performs section_flops / sections FP operations;
     the binding roofline is the one whose floor (work / peak) is longer."""
@@ -164,8 +176,7 @@ def roofline(st, dt, B, steps, pass_bytes, achieved_gbs, avg_launch_ms, sec_ms, 
     out = {"bound": "alu" if t_alu > t_hbm else "hbm"}
     out.update({k: main[k] for k in ("achieved", "peak", "unit", "frac")})
     out["traffic"] = traffic
-    out.update({"kernel": "k_section<%s, %d, ...> (one launch per section)"
-                          % ("double" if dt == B.QSV_C128 else "float", st["register_bits"]),
+    out.update({"kernel": section_kernel_name(kind, dt, B, st["register_bits"]) + " (one launch per section)",
                 "avg_launch_ms": round(avg_launch_ms, 3), "launches": launches,
                 "hbm": hbm, "alu": alu})
     return out
@@ -565,7 +576,8 @@ def main():
     if os.path.exists(PROFILE_TRAFFIC):
         with open(PROFILE_TRAFFIC) as f:
             prof = json.load(f)
-        if prof.get("kernel_source_hash") == kernel_source_hash() and prof.get("n") == n:
+        if (prof.get("kernel_source_hash") == kernel_source_hash() and prof.get("n") == n
+                and prof.get("options") == {k: opts.get(k) for k in sorted(prof.get("options", {}))}):
             traffic = prof.get("bytes_per_launch")
 
     rec = {
@@ -591,8 +603,8 @@ def main():
             "register_bits": st["register_bits"],
             "pinned_low_bits": st["pinned_low_bits"],
             "fusion_max_qubits": st["fusion_max_qubits"],
-            "section_kernel": "lds" if opts.get("section_kernel") == 1 else "registers",
-            "planner": {None: "default", 0: "default", 1: "greedy", 2: "beam"}.get(opts.get("planner"), "default"),
+            "section_kernel": SECTION_KERNELS.get(opts.get("section_kernel") or 0),
+            "planner": {None: "default", 0: "default", 1: "greedy", 2: "beam", 3: "exact"}.get(opts.get("planner"), "default"),
             "phases": st["n_phases"],
             "plan_s": round(t_plan, 4),
         },
@@ -606,7 +618,7 @@ def main():
         "final_norm": nrm,
         "parity": parity,
         "roofline": roofline(st, dt, B, args.steps, pass_bytes, achieved, avg_launch_ms,
-                             sec_ms, sec_launches, traffic),
+                             sec_ms, sec_launches, traffic, opts.get("section_kernel") or 0),
         "autotune": tune_rec,
     }
     if not args.skip_cpu:
