@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=33)
+    ap.add_argument("--n", type=int, default=None,
+                    help="qubits (default 33; 32 for the host workload, whose state must fit "
+                         "the pinned host memory a process may allocate)")
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--skip-pergate", action="store_true")
@@ -464,7 +466,11 @@ def main():
     if args.workload == "adjoint":
         return bench_adjoint(args, torch, B, W)
     if args.workload == "host":
+        if args.n is None:
+            args.n = 32
         return bench_host(args, torch, B, W)
+    if args.n is None:
+        args.n = 33
 
     n = args.n
     dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64
