@@ -305,3 +305,29 @@ def test_qv33_paired_beam_mirror_and_vs_registers(torch):
     del a
     assert abs(1.0 - abs(got[ys == 0][0]) ** 2) < 1e-12
     assert np.max(np.abs(got[ys != 0])) < 1e-7
+
+
+@pytest.mark.parametrize("n,dt,sizes", [(33, B.QSV_C128, [11, 11, 11]),
+                                        (34, B.QSV_C64, [12, 11, 11])])
+def test_grouped_qv_mfma_f5_vs_oracle(torch, n, dt, sizes):
+    """Fused blocks of up to 5 qubits applied as complex MFMA contractions at the
+    full size of the headline configurations: sampled amplitudes, including indices
+    beyond 2^32, against the product of small oracle runs."""
+    es = 16 if dt == B.QSV_C128 else 8
+    need_bytes(torch, es << n)
+    gates, groups = W.grouped_quantum_volume(n, sizes, n, 4)
+    ctx = B.Context(dt)
+    plan = B.Plan(n, gates, dt, section_kernel=B.QSV_KERNEL_MFMA, fusion_max_qubits=5,
+                  chunk_bits=12 if dt == B.QSV_C128 else 13, planner=B.QSV_PLANNER_BEAM)
+    assert plan.stats()["fusion_max_qubits"] == 5
+    st = torch.empty(1 << n, dtype=tdtype(torch, dt), device="cuda")
+    ctx.init_basis(st, n, 0)
+    ctx.apply(plan, st)
+    ys = sample_indices(n, 11)
+    got = gather(torch, st, ys)
+    nrm = ctx.norm(st, n).item()
+    del st
+    want = grouped.product_amplitudes(grouped.group_states(gates, groups), groups, ys)
+    rel = 1e-10 if dt == B.QSV_C128 else 1e-4
+    assert np.max(np.abs(got - want)) <= rel * np.max(np.abs(want))
+    assert abs(nrm - 1.0) < (1e-12 if dt == B.QSV_C128 else 1e-5)
