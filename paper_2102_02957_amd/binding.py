@@ -562,12 +562,17 @@ def state_candidates(dtype, n):
     out.append(dict(chunk_bits=min(base.chunk_bits, n), register_bits=base.register_bits,
                     pinned_low_bits=base.pinned_low_bits, fusion_max_qubits=2, io_phases=0,
                     planner=QSV_PLANNER_BEAM))
-    # paired phases (fixed register positions), default and beam planners
+    # paired phases (fixed register positions), default and beam planners, and the
+    # beam planner with one more pinned low bit (longer contiguous runs, more sections)
     for c in sorted({min(base.chunk_bits, n), min(base.chunk_bits - 1, n)}):
         for pl in (QSV_PLANNER_DEFAULT, QSV_PLANNER_BEAM):
             out.append(dict(chunk_bits=c, register_bits=4, pinned_low_bits=min(3, c - 4),
                             fusion_max_qubits=2, io_phases=0, planner=pl,
                             section_kernel=QSV_KERNEL_PAIRED))
+    c = min(base.chunk_bits, n)
+    out.append(dict(chunk_bits=c, register_bits=4, pinned_low_bits=min(4, c - 4),
+                    fusion_max_qubits=2, io_phases=0, planner=QSV_PLANNER_BEAM,
+                    section_kernel=QSV_KERNEL_PAIRED))
     # fused 4-qubit blocks on the matrix cores (LDS-resident chunk)
     c = min(base.chunk_bits, n)
     if c >= 9:
