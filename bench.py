@@ -67,9 +67,12 @@ def parse():
                     help="host workload: device memory for the slice buffers")
     ap.add_argument("--sections", type=int, default=3,
                     help="host workload: sections timed per step")
-    ap.add_argument("--workload", choices=["qv", "trajectories", "adjoint", "host"], default="qv",
+    ap.add_argument("--workload", choices=["qv", "trajectories", "adjoint", "host", "density"],
+                    default="qv",
                     help="qv: the headline blocked apply (default); trajectories: 512 noisy "
-                         "trajectories in one graph launch; adjoint: 20-qubit ansatz gradients")
+                         "trajectories in one graph launch; adjoint: 20-qubit ansatz gradients; "
+                         "host: state in pinned host memory; density: noisy 16-qubit density "
+                         "matrix")
     return ap.parse_args()
 
 
@@ -451,6 +454,88 @@ def bench_host(args, torch, B, W):
     print(json.dumps(rec), flush=True)
 
 
+def bench_density(args, torch, B, W):
+    """A noisy circuit on an n-qubit density matrix (default 16 qubits: rho holds 2^32
+    amplitudes, 64 GiB in complex128) through its 2n-qubit blocked plan (gates as U and
+    conj(U), channels as superoperator gates).  One step = one application of the whole
+    noisy circuit; value = sections x one pass of rho / wall time."""
+    n = args.n
+    dt = B.QSV_C128 if args.dtype == "c128" else B.QSV_C64
+    tdt = torch.complex128 if dt == B.QSV_C128 else torch.complex64
+    es = 16 if dt == B.QSV_C128 else 8
+    layers = 8
+    gates = W.noisy_density_circuit(n, layers, args.seed, p_depol=0.01, gamma=0.02, p_phase=0.005)
+    opts = dict(chunk_bits=args.chunk_bits, pinned_low_bits=args.pinned,
+                fusion_max_qubits=args.fusion, register_bits=args.register_bits,
+                section_kernel=args.section_kernel, planner=args.planner)
+    t0 = time.perf_counter()
+    plan = B.Plan.density(n, gates, dt, **opts)
+    t_plan = time.perf_counter() - t0
+    st = plan.stats()
+    S = st["n_sections"]
+    N2 = 2 * n
+    pass_bytes = 2.0 * (1 << N2) * es
+    ctx = B.Context(dt)
+    rho = torch.empty(1 << N2, dtype=tdt, device="cuda")
+    ctx.dm_init_basis(rho, n, 0)
+    for _ in range(max(1, args.warmup)):
+        ctx.apply(plan, rho)
+    torch.cuda.synchronize()
+    ctx.timing(True)
+    ctx.timing_read(0, reset=True)
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.apply(plan, rho)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    sec_ms, launches = ctx.timing_read(0, reset=True)
+    ctx.timing(False)
+    tr = ctx.dm_trace(rho, n).item()
+    purity = ctx.norm(rho, N2).item()
+    avg_launch_ms = sec_ms / max(1, launches)
+    rec = {
+        "metric": "density-matrix noisy circuit: blocked apply GB/s (%% HBM peak), %dq rho "
+                  "(%d-qubit plan) %s" % (n, N2, args.dtype),
+        "value": round(S * pass_bytes * args.steps / wall / 1e9, 2), "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 2), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if dt == B.QSV_C128 else "f32",
+        "data": "synthetic",
+        "config": {"workload": "%d-qubit density matrix, %d layers of U3 + depolarize(0.01), CX + "
+                               "amplitude damping(0.02), phase damping(0.005), seed %d"
+                               % (n, layers, args.seed),
+                   "ops": len(gates), "sections": S, "chunk_bits": st["chunk_bits"],
+                   "register_bits": st["register_bits"], "plan_s": round(t_plan, 3)},
+        "trace_error": abs(tr - 1.0), "purity": purity,
+        "ops_per_s": round(len(gates) * args.steps / wall, 1),
+        "roofline": roofline(st, dt, B, args.steps, pass_bytes,
+                             pass_bytes / (avg_launch_ms * 1e-3) / 1e9, avg_launch_ms, sec_ms,
+                             launches, None, opts.get("section_kernel") or 0),
+    }
+    if not args.skip_cpu:
+        with one_thread():
+            import oracle
+            ns = 6
+            small = W.noisy_density_circuit(ns, layers, args.seed, p_depol=0.01, gamma=0.02,
+                                            p_phase=0.005)
+            t2 = time.perf_counter()
+            reps = 0
+            while time.perf_counter() - t2 < 10.0 or reps == 0:
+                oracle.density.evolve(ns, small)
+                reps += 1
+            per_op = (time.perf_counter() - t2) / (reps * len(small))
+            # the oracle multiplies full 2^n x 2^n operators: cost grows as 8^n
+            t_full = per_op * len(gates) * 8.0 ** (n - ns)
+        rec["cpu_baseline"] = {
+            "value": S * pass_bytes / t_full / 1e9, "unit": "GB/s", "cores": 1,
+            "host_cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": "oracle.density.evolve of the %d-qubit version of the circuit, %d run(s) "
+                      "in %.1f s; time per op scaled x8^%d (full-operator products) x%d ops "
+                      "(extrapolated %.3g s per step)" % (ns, reps, per_op * reps * len(small),
+                                                          n - ns, len(gates), t_full)}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -469,6 +554,10 @@ def main():
         if args.n is None:
             args.n = 32
         return bench_host(args, torch, B, W)
+    if args.workload == "density":
+        if args.n is None:
+            args.n = 16
+        return bench_density(args, torch, B, W)
     if args.n is None:
         args.n = 33
 
