@@ -21,6 +21,7 @@
 //      consecutive register gates into dense matrices of at most f qubits;
 //   4. the per-gate op list (one kernel per gate, the unblocked baseline).
 #include <algorithm>
+#include <functional>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -1229,34 +1230,97 @@ static void lower_section_paired(Plan &P, int si) {
         if (real_op) P.flops += 32.0 * std::ldexp(1.0, n);
     };
 
-    std::vector<int> rem = S.gates;
-    while (!rem.empty()) {
-        const GateRec &g0 = P.gates[rem[0]];
-        const int a0 = g0.q[0], a1 = g0.q[1];
-        const uint64_t maskA = g0.qmask;
-        std::vector<cd> mA = g0.m, mB = ident;
-        int b0 = -1, b1 = -1;
-        uint64_t maskB = 0, blocked = 0;
-        std::vector<int> next;
-        for (size_t t = 1; t < rem.size(); ++t) {
-            const GateRec &g = P.gates[rem[t]];
-            if (g.qmask & blocked) {
-                blocked |= g.qmask;
-                next.push_back(rem[t]);
-            } else if (g.qmask == maskA) {
-                mA = matmul(pair_matrix(g, a0), mA, 4);
-            } else if (!maskB && !(g.qmask & maskA)) {
-                b0 = g.q[0];
-                b1 = g.q[1];
-                maskB = g.qmask;
-                mB = g.m;
-            } else if (maskB && g.qmask == maskB) {
-                mB = matmul(pair_matrix(g, b0), mB, 4);
-            } else {
-                blocked |= g.qmask;
-                next.push_back(rem[t]);
+    // Tasks: chains of gates on one qubit pair with nothing in between on either
+    // qubit, fused into one 4 x 4 matrix; a task depends on the last earlier task
+    // on each of its qubits.
+    struct Task {
+        uint64_t mask;
+        int q0, q1;
+        std::vector<cd> m;
+        std::vector<int> succ;
+        int npred = 0, label = 0;
+    };
+    std::vector<Task> tasks;
+    {
+        std::vector<int> last(n, -1);
+        for (int gi : S.gates) {
+            const GateRec &g = P.gates[gi];
+            const int x = g.q[0], y = g.q[1];
+            const int tx = last[x], ty = last[y];
+            if (tx >= 0 && tx == ty && tasks[tx].mask == g.qmask) {
+                tasks[tx].m = matmul(pair_matrix(g, tasks[tx].q0), tasks[tx].m, 4);
+                continue;
             }
+            Task t;
+            t.mask = g.qmask;
+            t.q0 = x;
+            t.q1 = y;
+            t.m = g.m;
+            const int id = (int)tasks.size();
+            if (tx >= 0) {
+                tasks[tx].succ.push_back(id);
+                ++t.npred;
+            }
+            if (ty >= 0 && ty != tx) {
+                tasks[ty].succ.push_back(id);
+                ++t.npred;
+            }
+            tasks.push_back(std::move(t));
+            last[x] = last[y] = id;
         }
+    }
+    // Two tasks per phase (two register pairs) with unit-time tasks and precedence:
+    // the Coffman-Graham order (labels from the sinks up, smallest decreasing list
+    // of successor labels first) scheduled two at a time by highest label needs the
+    // fewest phases.
+    {
+        const int T = (int)tasks.size();
+        for (int k = 1; k <= T; ++k) {
+            int pick = -1;
+            std::vector<int> best;
+            for (int t = T - 1; t >= 0; --t) {
+                if (tasks[t].label) continue;
+                bool ok = true;
+                std::vector<int> key;
+                for (int u : tasks[t].succ) {
+                    if (!tasks[u].label) ok = false;
+                    key.push_back(tasks[u].label);
+                }
+                if (!ok) continue;
+                std::sort(key.begin(), key.end(), std::greater<int>());
+                if (pick < 0 || key < best) {
+                    pick = t;
+                    best.swap(key);
+                }
+            }
+            tasks[pick].label = k;
+        }
+    }
+    std::vector<int> ready;
+    for (int t = 0; t < (int)tasks.size(); ++t)
+        if (tasks[t].npred == 0) ready.push_back(t);
+    while (!ready.empty()) {
+        std::sort(ready.begin(), ready.end(),
+                  [&](int a, int b) { return tasks[a].label > tasks[b].label; });
+        const Task &TA = tasks[ready[0]];
+        const int a0 = TA.q0, a1 = TA.q1;
+        const std::vector<cd> mA = TA.m;
+        std::vector<cd> mB = ident;
+        int b0 = -1, b1 = -1;
+        uint64_t maskB = 0;
+        std::vector<int> done = {ready[0]};
+        if (ready.size() > 1) {
+            const Task &TB = tasks[ready[1]];
+            b0 = TB.q0;
+            b1 = TB.q1;
+            maskB = TB.mask;
+            mB = TB.m;
+            done.push_back(ready[1]);
+        }
+        ready.erase(ready.begin(), ready.begin() + (long)done.size());
+        for (int t : done)
+            for (int u : tasks[t].succ)
+                if (--tasks[u].npred == 0) ready.push_back(u);
         // register positions: (a0, a1, b0, b1), filled from the highest slots when
         // the phase has one pair; then the other local qubits by ascending slot
         std::vector<int> regq = {a0, a1};
@@ -1279,7 +1343,6 @@ static void lower_section_paired(Plan &P, int si) {
         push_op(2, mB, maskB != 0);
         ph.op_end = (uint32_t)P.dops.size();
         P.dphase.push_back(ph);
-        rem.swap(next);
     }
     P.kmax = std::max(P.kmax, 2);
     ds.phase_end = (uint32_t)P.dphase.size();
