@@ -448,3 +448,60 @@ def test_lds_kernel_plan_validation():
     assert e.value.status == -4
     with pytest.raises(B.QsvError):
         B.Plan(n, W.ghz(n), B.QSV_C128, section_kernel=7)
+
+
+def _min_two_wide_steps(pairs):
+    """Fewest steps that run the 2-qubit gates `pairs` (in circuit order) two at a
+    time, after fusing each chain of gates on one pair with nothing in between on
+    either qubit: breadth-first search over the sets of chains already run (a chain
+    may run once every chain it depends on has run in an earlier step)."""
+    chains, last = [], {}
+    deps = []
+    for a, b in pairs:
+        ta, tb = last.get(a), last.get(b)
+        if ta is not None and ta == tb and chains[ta] == frozenset((a, b)):
+            continue
+        chains.append(frozenset((a, b)))
+        deps.append({t for t in (ta, tb) if t is not None})
+        last[a] = last[b] = len(chains) - 1
+    full = (1 << len(chains)) - 1
+    frontier, seen, steps = {0}, {0}, 0
+    while full not in frontier:
+        nxt = set()
+        for done in frontier:
+            ready = [t for t in range(len(chains)) if not (done >> t) & 1
+                     and all((done >> d) & 1 for d in deps[t])]
+            picks = [(x, y) for i, x in enumerate(ready) for y in ready[i + 1:]] or [(ready[0],)]
+            for pick in picks:
+                s = done
+                for t in pick:
+                    s |= 1 << t
+                if s not in seen:
+                    seen.add(s)
+                    nxt.add(s)
+        frontier = nxt
+        steps += 1
+    return steps
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_paired_phases_are_minimal(seed):
+    """Paired plans run each section in the fewest phases of two fused gate chains
+    (checked against a breadth-first search per section), and their exported plan
+    equals the circuit."""
+    n, c = 9, 6
+    gates = W.quantum_volume(n, 6, 300 + seed)
+    plan = B.Plan(n, gates, B.QSV_C128, chunk_bits=c, pinned_low_bits=0,
+                  section_kernel=B.QSV_KERNEL_PAIRED)
+    want, cur = 0, None
+    for op in plan.export():
+        if op[0] == "begin":
+            cur = []
+        elif op[0] == "gate":
+            cur.append(tuple(op[2]))
+        elif op[0] == "end":
+            want += _min_two_wide_steps(cur)
+    assert plan.stats()["n_phases"] == want
+    st, _ = plan_matches_circuit(n, gates, chunk_bits=c, pinned_low_bits=0,
+                                 section_kernel=B.QSV_KERNEL_PAIRED)
+    assert st["n_phases"] == want
