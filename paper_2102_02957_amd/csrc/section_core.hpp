@@ -177,11 +177,26 @@ template <int... P> __host__ __device__ constexpr int dep_pos(int l) {
     return out;
 }
 
+// Copies a uniform complex value into VGPRs.  The empty asm hides the value's
+// uniformity from the compiler, which would otherwise keep it in SGPRs.
+template <typename V> __device__ __forceinline__ V to_vgpr(V u) {
+    asm volatile("" : "+v"(u.x), "+v"(u.y));
+    return u;
+}
+
 // dense 2^K x 2^K matrix (row-major, uniform memory) on register positions P...
-template <typename V, int R, int... P>
-__device__ __forceinline__ void dense_apply(V (&a)[1 << R], cptr<V> m) {
+// STAGE reads the matrix into VGPRs once, before the amplitude groups.  On gfx950
+// an FP32 FMA with an SGPR operand issues at half the rate of one with VGPR
+// operands (FP64 issue does not depend on it).  The paired kernel stages its FP32
+// 2-qubit matrices (32 floats); the register kernels do not, because the extra
+// VGPRs cost them a wave per SIMD, which measured slower than the half-rate FMAs.
+template <bool STAGE, typename V, int R, int... P>
+__device__ __forceinline__ void dense_apply_m(V (&a)[1 << R], cptr<V> m) {
     constexpr int K = sizeof...(P);
     constexpr int D = 1 << K;
+    V u[STAGE ? D * D : 1];
+    if constexpr (STAGE)
+        static_for<D * D>([&](auto I) __attribute__((always_inline)) { u[I.value] = to_vgpr(ldc(m + I.value)); });
     static_for<(1 << (R - K))>([&](auto G) __attribute__((always_inline)) {
         constexpr int b = dep_rest<R, P...>(G.value);
         V in[D];
@@ -190,12 +205,20 @@ __device__ __forceinline__ void dense_apply(V (&a)[1 << R], cptr<V> m) {
             V acc;
             acc.x = 0;
             acc.y = 0;
-            static_for<D>([&](auto L) __attribute__((always_inline)) { acc = cfma(ldc(m + (ROW.value * D + L.value)), in[L.value], acc); });
+            static_for<D>([&](auto L) __attribute__((always_inline)) {
+                constexpr int e = ROW.value * D + L.value;
+                if constexpr (STAGE) acc = cfma(u[e], in[L.value], acc);
+                else acc = cfma(ldc(m + e), in[L.value], acc);
+            });
             a[b | dep_pos<P...>(ROW.value)] = acc;
         });
         // one amplitude group at a time: keeps the live temporaries to one group
         __builtin_amdgcn_sched_barrier(0);
     });
+}
+template <typename V, int R, int... P>
+__device__ __forceinline__ void dense_apply(V (&a)[1 << R], cptr<V> m) {
+    dense_apply_m<false, V, R, P...>(a, m);
 }
 
 // dispatch of runtime positions (ascending) to the compile-time instances
@@ -668,8 +691,9 @@ __device__ __forceinline__ void run_chunk_paired(typename Amp<T>::V *__restrict_
     for (int p = 0; p < nph; ++p) {
         const cptr<DevPhase> P = ph + p;
         const uint32_t o = P->op_begin;
-        dense_apply<V, R, 0, 1>(a, mats + ops[o].arg);
-        dense_apply<V, R, 2, 3>(a, mats + ops[o + 1].arg);
+        constexpr bool STAGE = sizeof(V) == 8;  // FP32 entries to VGPRs
+        dense_apply_m<STAGE, V, R, 0, 1>(a, mats + ops[o].arg);
+        dense_apply_m<STAGE, V, R, 2, 3>(a, mats + ops[o + 1].arg);
         if (p + 1 < nph)
             chunk_transpose<V, R, true>(a, lds, P->wr, ph[p + 1].rd, P->xw, P->xr, tid, TB, true);
     }
