@@ -385,7 +385,12 @@ __device__ __forceinline__ void chunk_scatter(const V (&a)[1 << R], V *__restric
                                               cptr<uint8_t> phys_tab, uint64_t base,
                                               unsigned tid, int TB) {
     const Bytes16 phys = ld16(phys_tab);
-    V *tp = st + (base | thread_offset<V, R>(phys, tid, TB));
+    // A fresh copy of tid: otherwise the compiler computes the thread offset's
+    // per-bit terms before the phase loop (or shares the gather's) and holds
+    // them in VGPRs through every phase.
+    unsigned t = tid;
+    asm volatile("" : "+v"(t));
+    V *tp = st + (base | thread_offset<V, R>(phys, t, TB));
     static_for<(1 << R)>([&](auto I) __attribute__((always_inline)) {
         uint64_t ro = 0;  // uniform
         static_for<R>([&](auto B) __attribute__((always_inline)) {

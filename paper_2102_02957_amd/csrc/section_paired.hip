@@ -14,8 +14,12 @@ using namespace sec;
 
 namespace {
 
+// The FP32 instance fits in 80 VGPRs without spilling, which gives 6 waves per
+// SIMD: three workgroups of 512 threads per CU.  At 5 waves it holds only two,
+// and FP32 FMAs reach full rate only while two waves per SIMD issue.  The FP64
+// instance keeps the compiler's choice (105 VGPRs; 80 would spill).
 template <typename T>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1)))
 k_section_paired(typename Amp<T>::V *__restrict__ state, int n, const DevSection *__restrict__ secs_g,
                  int sec, const DevPhase *__restrict__ phases_g, const DevOp *__restrict__ ops_g,
                  const typename Amp<T>::V *__restrict__ mats_g) {
