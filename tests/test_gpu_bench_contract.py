@@ -1,6 +1,8 @@
 """The benchmark's one-line JSON record: required keys, units and the roofline
-object, on a small Quantum-Volume run (24 qubits, library defaults)."""
+object, on a small Quantum-Volume run (24 qubits, library defaults); its refusal
+of several GPUs; and the committed traffic profile it reads."""
 
+import importlib.util
 import json
 import os
 import subprocess
@@ -39,3 +41,22 @@ def test_bench_refuses_several_gpus():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120, cwd=ROOT)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_traffic_profile_matches_sources():
+    """The committed PMC traffic profile of the headline kernel was taken on the
+    current section-kernel sources (the benchmark reports it as roofline.traffic
+    only then), and its figures agree with one another."""
+    spec = importlib.util.spec_from_file_location("bench_for_test", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    with open(bench.PROFILE_TRAFFIC) as f:
+        prof = json.load(f)
+    assert prof["kernel_source_hash"] == bench.kernel_source_hash()
+    scaled = 1024.0 * (prof["fetch_kib_per_dispatch"] * prof["fetch_scale"]
+                       + prof["write_kib_per_dispatch"] * prof["write_scale"])
+    assert abs(scaled - prof["bytes_per_launch"]) <= 1e-9 * scaled
+    algorithmic = 2 * (1 << prof["n"]) * 16  # one read and one write of the complex128 state
+    assert prof["algorithmic_bytes_per_launch"] == algorithmic
+    assert abs(prof["ratio_to_algorithmic"] - scaled / algorithmic) < 1e-9
+    assert 1.0 <= prof["ratio_to_algorithmic"] < 1.05
