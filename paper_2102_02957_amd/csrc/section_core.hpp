@@ -187,9 +187,10 @@ template <typename V> __device__ __forceinline__ V to_vgpr(V u) {
 // dense 2^K x 2^K matrix (row-major, uniform memory) on register positions P...
 // STAGE reads the matrix into VGPRs once, before the amplitude groups.  On gfx950
 // an FP32 FMA with an SGPR operand issues at half the rate of one with VGPR
-// operands (FP64 issue does not depend on it).  The paired kernel stages its FP32
-// 2-qubit matrices (32 floats); the register kernels do not, because the extra
-// VGPRs cost them a wave per SIMD, which measured slower than the half-rate FMAs.
+// operands (FP64 issue does not depend on it).  The paired kernel and the batch
+// kernel stage their FP32 1- and 2-qubit matrices (up to 32 floats).  The
+// section register kernels do not: measured, staging made them slower or no
+// faster (at r = 5 it costs a wave per SIMD).
 template <bool STAGE, typename V, int R, int... P>
 __device__ __forceinline__ void dense_apply_m(V (&a)[1 << R], cptr<V> m) {
     constexpr int K = sizeof...(P);
@@ -221,22 +222,23 @@ __device__ __forceinline__ void dense_apply(V (&a)[1 << R], cptr<V> m) {
     dense_apply_m<false, V, R, P...>(a, m);
 }
 
-// dispatch of runtime positions (ascending) to the compile-time instances
-template <typename V, int R, int P0 = 0>
+// dispatch of runtime positions (ascending) to the compile-time instances;
+// STAGE as in dense_apply_m
+template <typename V, int R, bool STAGE = false, int P0 = 0>
 __device__ __forceinline__ void dispatch1(V (&a)[1 << R], int a0, cptr<V> m) {
     if constexpr (P0 < R) {
-        if (a0 == P0) dense_apply<V, R, P0>(a, m);
-        else dispatch1<V, R, P0 + 1>(a, a0, m);
+        if (a0 == P0) dense_apply_m<STAGE, V, R, P0>(a, m);
+        else dispatch1<V, R, STAGE, P0 + 1>(a, a0, m);
     }
 }
-template <typename V, int R, int P0 = 0, int P1 = 1>
+template <typename V, int R, bool STAGE = false, int P0 = 0, int P1 = 1>
 __device__ __forceinline__ void dispatch2(V (&a)[1 << R], int a0, int a1, cptr<V> m) {
     if constexpr (P0 < R - 1) {
         if constexpr (P1 < R) {
-            if (a0 == P0 && a1 == P1) dense_apply<V, R, P0, P1>(a, m);
-            else dispatch2<V, R, P0, P1 + 1>(a, a0, a1, m);
+            if (a0 == P0 && a1 == P1) dense_apply_m<STAGE, V, R, P0, P1>(a, m);
+            else dispatch2<V, R, STAGE, P0, P1 + 1>(a, a0, a1, m);
         } else {
-            dispatch2<V, R, P0 + 1, P0 + 2>(a, a0, a1, m);
+            dispatch2<V, R, STAGE, P0 + 1, P0 + 2>(a, a0, a1, m);
         }
     }
 }
@@ -534,7 +536,7 @@ __device__ __forceinline__ void chunk_transpose(V (&a)[1 << R], V *lds, cptr<uin
 
 // Forward application of the ops [o_begin, o_end) of one phase to the
 // registers.  pbase = thread index << R; base = the chunk's physical base index.
-template <typename T, int R, int KMAX, bool DENSE_ONLY = false>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool STAGE = false>
 __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<DevOp> ops,
                                           uint32_t o_begin, uint32_t o_end,
                                           cptr<typename Amp<T>::V> mats,
@@ -553,8 +555,8 @@ __device__ __forceinline__ void chunk_ops(typename Amp<T>::V (&a)[1 << R], cptr<
         const uint32_t k = op.k;
         if (type == OP_DENSE) {
             const cptr<V> mm = mats + op.arg;
-            if (k == 1) dispatch1<V, R>(a, op.a[0], mm);
-            else if (k == 2) dispatch2<V, R>(a, op.a[0], op.a[1], mm);
+            if (k == 1) dispatch1<V, R, STAGE>(a, op.a[0], mm);
+            else if (k == 2) dispatch2<V, R, STAGE>(a, op.a[0], op.a[1], mm);
             else if constexpr (KMAX >= 3) {
                 if (k == 3) dispatch3<V, R>(a, op.a[0], op.a[1], op.a[2], mm);
                 else if constexpr (KMAX >= 4) {
@@ -640,7 +642,7 @@ __device__ __forceinline__ uint64_t chunk_base(cptr<DevSection> S, uint64_t chun
 }
 
 // All phases of one section on the registers of one chunk (no HBM traffic).
-template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool SPLIT = true>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool SPLIT = true, bool STAGE = false>
 __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cptr<DevPhase> ph,
                                              int nph, cptr<DevOp> ops,
                                              cptr<typename Amp<T>::V> mats,
@@ -651,14 +653,14 @@ __device__ __forceinline__ void chunk_phases(typename Amp<T>::V (&a)[1 << R], cp
     const uint32_t pbase = tid << R;
     for (int p = 0; p < nph; ++p) {
         const cptr<DevPhase> P = ph + p;
-        chunk_ops<T, R, KMAX, DENSE_ONLY>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
+        chunk_ops<T, R, KMAX, DENSE_ONLY, STAGE>(a, ops, P->op_begin, P->op_end, mats, ptab, pbase, base);
         if (p + 1 < nph)
             chunk_transpose<V, R, SPLIT>(a, lds, P->wr, ph[p + 1].rd, P->xw, P->xr, tid, TB, active);
     }
 }
 
 // One chunk of one section, forward: gather, phases, scatter.
-template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool SPLIT = true>
+template <typename T, int R, int KMAX, bool DENSE_ONLY = false, bool SPLIT = true, bool STAGE = false>
 __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
                                           cptr<DevSection> S, cptr<DevPhase> phases,
                                           cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
@@ -672,7 +674,7 @@ __device__ __forceinline__ void run_chunk(typename Amp<T>::V *__restrict__ st,
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
     if (active) chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
-    chunk_phases<T, R, KMAX, DENSE_ONLY, SPLIT>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
+    chunk_phases<T, R, KMAX, DENSE_ONLY, SPLIT, STAGE>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
     if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
     if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
 }
@@ -717,7 +719,7 @@ template <typename V, int R> __device__ __forceinline__ double reg_norm2(const V
 // Same as run_chunk, and also returns (in thread 0) the chunk's FP64 sum of
 // |a|^2 after the section, reduced in a fixed order through `red` (blockDim.x
 // doubles of LDS).
-template <typename T, int R, int KMAX, bool SPLIT = true>
+template <typename T, int R, int KMAX, bool SPLIT = true, bool STAGE = false>
 __device__ __forceinline__ double run_chunk_norm(typename Amp<T>::V *__restrict__ st,
                                                  cptr<DevSection> S, cptr<DevPhase> phases,
                                                  cptr<DevOp> ops, cptr<typename Amp<T>::V> mats,
@@ -731,7 +733,7 @@ __device__ __forceinline__ double run_chunk_norm(typename Amp<T>::V *__restrict_
     const int nph = (int)(S->phase_end - S->phase_begin);
     V a[1 << R];
     if (active) chunk_gather<V, R>(a, st, S->gather_phys, base, tid, TB);
-    chunk_phases<T, R, KMAX, false, SPLIT>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
+    chunk_phases<T, R, KMAX, false, SPLIT, STAGE>(a, ph, nph, ops, mats, ptab, base, lds, TB, active);
     if (S->flags & SEC_SYNC_SCATTER) gather_scatter_barrier();
     if (active) chunk_scatter<V, R>(a, st, S->scatter_phys, base, tid, TB);
     red[tid] = active ? reg_norm2<V, R>(a) : 0.0;
